@@ -1,0 +1,61 @@
+"""Seeded synthetic sample points (the random inputs of the method).
+
+This module holds no arithmetic of the method itself: it only draws the
+standard-normal KL coordinates xi that both the HIP library and the CPU
+oracle consume, so that every form sees bit-identical inputs.
+
+  - Monte Carlo (Section 2.1, Eq. (3)): i.i.d. N(0,1) from numpy's PCG64,
+    seeded by SeedSequence([seed, config, level, purpose]); levels use
+    independent streams, as the estimator requires (Eq. (5)).
+  - Randomised QMC (Section 2.4): a scrambled Sobol' point set (scipy's
+    Owen-type scrambling), then R random digital shifts (XOR of 30-bit
+    integers), mapped through the inverse normal CDF at the dyadic cell
+    midpoints u = (k + 1/2) 2^-30 so that u is never 0 or 1. Dimension m of
+    the point set drives KL mode m (largest eigenvalue first). Samples are
+    grouped shift-major: [shift][point][mode].
+"""
+import numpy as np
+
+SEED = 20191010
+PURPOSE_ESTIMATOR = 0
+PURPOSE_PILOT = 1
+PURPOSE_CNN_TRAIN = 2
+PURPOSE_CNN_TEST = 3
+
+_BITS = 30
+
+
+def mc_normals(n, M, config, level, purpose=PURPOSE_ESTIMATOR, seed=SEED, offset=0):
+    """[n, M] float64 standard normals for (config, level, purpose).
+
+    `offset` skips that many leading rows of the same stream, so a batch can
+    be regenerated in pieces with identical values.
+    """
+    ss = np.random.SeedSequence([seed, config, level, purpose])
+    g = np.random.Generator(np.random.PCG64(ss))
+    if offset:
+        g.standard_normal((offset, M))
+    return g.standard_normal((n, M))
+
+
+def sobol_ints(M, m_log2, config, level, seed=SEED):
+    """Scrambled Sobol' points as exact 30-bit integers, [2^m_log2, M] uint64."""
+    from scipy.stats import qmc
+    scr = int(np.random.SeedSequence([seed, config, level, 7]).generate_state(1)[0])
+    s = qmc.Sobol(d=M, scramble=True, bits=_BITS, seed=scr)
+    u = s.random_base2(m_log2)
+    return np.round(u * float(1 << _BITS)).astype(np.uint64)
+
+
+def rqmc_normals(M, m_log2, nshift, config, level, seed=SEED):
+    """[nshift * 2^m_log2, M] standard normals, grouped shift-major."""
+    from scipy.special import ndtri
+    base = sobol_ints(M, m_log2, config, level, seed)
+    ss = np.random.SeedSequence([seed, config, level, 8])
+    g = np.random.Generator(np.random.PCG64(ss))
+    shifts = g.integers(0, 1 << _BITS, size=(nshift, M), dtype=np.uint64)
+    out = np.empty((nshift, base.shape[0], M))
+    for r in range(nshift):
+        k = np.bitwise_xor(base, shifts[r][None, :])
+        out[r] = ndtri((k.astype(np.float64) + 0.5) * (1.0 / float(1 << _BITS)))
+    return out.reshape(nshift * base.shape[0], M)
