@@ -1,0 +1,200 @@
+/*
+ * fmgmc.h - C ABI of the MI355X (gfx950) library for the full-multigrid
+ * multilevel (quasi-)Monte Carlo method for single-phase Darcy flow with a
+ * log-normal random permeability (Liu, Li, Sun, Yu, arXiv:1910.04727).
+ *
+ * Problem solved per sample (Section 2.1 Eq. (1); Case II of Table 1):
+ *   -div(k grad p) = 0 on the unit square, p = p_west on x = 0, p = p_east on
+ *   x = 1, no flow on y = 0 and y = 1; QoI = outflow through x = 1.
+ *   Cell-centred finite volumes on an n x n grid with harmonic-mean face
+ *   transmissibilities (Section 3.1 (1)).
+ * Field (Section 3.1 (2)): k = exp(g), g a truncated Karhunen-Loeve expansion
+ *   of the separable exponential covariance sigma^2 exp(-|dx|/l - |dy|/l),
+ *   sampled at cell lower-left corners; xi (the KL coordinates) are inputs.
+ * Hierarchy (Section 3.1 (1), Section 2.5): MLMC level l solves on the grid
+ *   n_l = n0 * 2^l; the coarse-mesh QoI Q^c_l is read from the full-multigrid
+ *   stage on n_l / 2 of the same pass that yields Q^f_l (Algorithm 3), with
+ *   the coefficient coarsened by injection (Section 2.5, Coarsening).
+ * Estimators (Section 2.1 Eqs. (2)-(5); Section 2.4): per-level means and
+ *   variances of Y_l = Q^f_l - Q^c_l, MLMC sum and its variance; randomised
+ *   QMC by per-shift means.
+ *
+ * Conventions for every call:
+ *   - returns FMGMC_OK (0) on success or a negative FMGMC_E* code; the
+ *     message of the last error on the calling thread is fmgmc_last_error().
+ *   - array pointers may be host or device memory (detected per call); all
+ *     arrays are dense, C order. No pointer is retained after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Device work is
+ *     enqueued on it. fmgmc_solve_level and fmgmc_estimate synchronise the
+ *     stream (they read per-sample convergence counters / results back);
+ *     fmgmc_synthesize_field returns without synchronising when both arrays
+ *     are in device memory.
+ *   - one context per host thread; a context is bound to one device.
+ */
+#ifndef FMGMC_H
+#define FMGMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FMGMC_OK = 0,
+    FMGMC_EINVAL = -1,     /* bad argument */
+    FMGMC_ENOMEM = -2,     /* device or host allocation failed */
+    FMGMC_EHIP = -3,       /* HIP runtime error */
+    FMGMC_ENOTCONV = -4,   /* some sample did not reach rel_tol (outputs are written, flags set) */
+    FMGMC_ENONFINITE = -5  /* some sample produced a non-finite residual (flags set) */
+};
+
+/* per-sample flag bits */
+enum {
+    FMGMC_FLAG_NOTCONV = 1,    /* a QoI stage stopped at max_cycles above rel_tol */
+    FMGMC_FLAG_NONFINITE = 2   /* non-finite residual or coefficient */
+};
+
+enum { FMGMC_COV_SEPARABLE_EXP = 0 };
+enum { FMGMC_SOLVER_FP64 = 0, FMGMC_SOLVER_FP32_IR = 1 };
+enum { FMGMC_KL_FP64 = 0, FMGMC_KL_FP32 = 1, FMGMC_KL_BF16 = 2 };
+
+/* Random field (Section 3.1 (2)). */
+typedef struct {
+    double sigma2;     /* variance of g, > 0 */
+    double corr_len;   /* correlation length l of exp(-|dx|/l - |dy|/l), > 0 */
+    int32_t n_modes;   /* M, number of 2-D KL modes kept (largest first), 1..4096 */
+    int32_t cov_kind;  /* FMGMC_COV_SEPARABLE_EXP */
+} fmgmc_field;
+
+/* Level hierarchy (Section 3.1 (1)). */
+typedef struct {
+    int32_t n_levels;    /* MLMC levels 0 .. n_levels-1 */
+    int32_t n0;          /* fine grid of level 0 (power of two); level l uses n0 << l */
+    int32_t n_coarsest;  /* multigrid coarsest grid, 4; n0 >= n_coarsest */
+    int32_t reserved;    /* 0 */
+    double p_west;       /* Dirichlet pressure at x = 0 */
+    double p_east;       /* Dirichlet pressure at x = 1 */
+} fmgmc_hier;
+
+/* Solver options. */
+typedef struct {
+    int32_t solver;        /* FMGMC_SOLVER_FP64 or FMGMC_SOLVER_FP32_IR */
+    int32_t kl_prec;       /* FMGMC_KL_FP64 / FP32 / BF16 (arithmetic of the KL contraction) */
+    int32_t nu1, nu2;      /* pre/post red-black Gauss-Seidel sweeps per V-cycle, 1..2 */
+    int32_t max_cycles;    /* cap on V-cycles per QoI stage (>= 1) */
+    int32_t inner_cycles;  /* FP32 V-cycles per FP64 refinement step (FP32_IR), >= 1 */
+    int32_t max_batch;     /* samples resident on the device at once (0 = library default) */
+    int32_t reserved;      /* 0 */
+    double rel_tol;        /* stop when ||b - A p||_2 <= rel_tol ||b||_2 at a QoI stage */
+} fmgmc_opts;
+
+typedef struct fmgmc_ctx fmgmc_ctx;
+
+/*
+ * Creates a context on HIP device `device`: builds the KL mode table
+ * (Section 3.1 (2): 1-D roots, eigenvalues sigma^2 theta_a theta_b sorted
+ * descending, exact ties by (a, b) ascending) and reserves device memory for
+ * opts->max_batch samples of the finest level. The structs are copied.
+ * Errors: EINVAL (inconsistent sizes), ENOMEM, EHIP.
+ */
+int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hier,
+                 const fmgmc_opts *opts, int device);
+
+/* Releases every resource of the context. NULL is accepted. */
+int fmgmc_destroy(fmgmc_ctx *ctx);
+
+/*
+ * Copies the KL mode table in xi-column order: a[m], b[m] = 0-based 1-D mode
+ * indices along x and y, lambda[m] = sigma^2 theta_a theta_b (host arrays of
+ * at least `cap` entries). Returns the number of modes written (>= 0) or an
+ * error code.
+ */
+int fmgmc_mode_table(const fmgmc_ctx *ctx, int32_t *a, int32_t *b, double *lambda, int32_t cap);
+
+/*
+ * Synthesises the permeability k = exp(g) on the n x n grid of MLMC level
+ * `level` for n_samples samples (Section 3.1 (2), corner sampling) with the
+ * context's kl_prec. xi is [n_samples][n_modes]; k_out is [n_samples][n][n]
+ * (double). Errors: EINVAL, EHIP.
+ */
+int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi,
+                double *k_out, void *stream);
+
+/*
+ * Batched FMG-MLMC solve of one MLMC level (Algorithm 3): per sample, the
+ * field from xi[s][:], its injected pyramid, one full-multigrid pass whose
+ * stage on n_l/2 gives q_coarse[s] (0 on level 0) and whose stage on n_l gives
+ * q_fine[s], each driven to rel_tol.
+ *   xi      [n_samples][n_modes] double
+ *   q_fine, q_coarse  [n_samples] double
+ *   cycles  [n_samples][2] int32: V-cycles at the coarse / fine QoI stage (nullable)
+ *   flags   [n_samples] uint8, FMGMC_FLAG_* bits (nullable)
+ * Returns OK, ENOTCONV or ENONFINITE (outputs written in all three cases),
+ * or EINVAL / ENOMEM / EHIP.
+ */
+int fmgmc_solve_level(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi,
+                      double *q_fine, double *q_coarse, int32_t *cycles, uint8_t *flags,
+                      void *stream);
+
+/* Per-level statistics filled by fmgmc_estimate. */
+typedef struct {
+    int64_t n;        /* samples */
+    double mean_y;    /* mean of Y = Q^f - Q^c (the level term of Eq. (3)) */
+    double var_y;     /* sample variance of Y (N - 1), or for RQMC the variance of mean_y */
+    double mean_qf;
+    double var_qf;
+    double mean_qc;
+} fmgmc_level_est;
+
+/*
+ * MLMC / MLQMC estimator (Section 2.1 Eqs. (2)-(5), Section 2.4) on the
+ * device with compensated (Neumaier) sums in a fixed order.
+ *   qf[l], qc[l]: n[l] samples of level l (host or device).
+ *   n_shifts == 1: Monte Carlo; var_y is the sample variance of Y_l and
+ *     *var_of_mean = sum_l var_y[l] / n[l].
+ *   n_shifts  > 1: randomised QMC, samples grouped shift-major
+ *     [shift][point]; mean_y is the mean of the per-shift means and var_y is
+ *     sum_r (Ybar_r - mean_y)^2 / (R (R - 1)); *var_of_mean = sum_l var_y[l].
+ *   levels[l] receives the per-level numbers; *mean = sum_l mean_y[l].
+ */
+int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf,
+                   const double *const *qc, int32_t n_shifts, fmgmc_level_est *levels,
+                   double *mean, double *var_of_mean, void *stream);
+
+/*
+ * Host-only (no device needed): the KL mode table of fmgmc_create for the
+ * given field, written to host arrays of n_modes entries (same layout as
+ * fmgmc_mode_table). Errors: EINVAL.
+ */
+int fmgmc_kl_modes(double sigma2, double corr_len, int32_t n_modes, int32_t *a, int32_t *b,
+                   double *lambda);
+
+/*
+ * Measurement hooks (not part of the method). With profiling enabled, every
+ * launch of the kernel classes below on the finest grid of a solve is
+ * bracketed by HIP events recorded on the launch stream, and its algorithmic
+ * traffic (each operand read once, each result written once; flops for the
+ * KL contraction) is accumulated from the number of samples still iterating.
+ * Kinds: 0 pre-smoothing + residual + restriction pass, 1 prolongation +
+ * post-smoothing pass (+ residual norm, QoI), 2 FP64 refinement pass,
+ * 3 KL synthesis, 4 coarse-grid V-cycle in LDS.
+ * fmgmc_profile_read synchronises, returns the summed kernel time in ms,
+ * the launch count and the algorithmic bytes (flops for kind 3), and clears
+ * the kind's record.
+ */
+enum { FMGMC_PROF_PRE = 0, FMGMC_PROF_POST = 1, FMGMC_PROF_IR = 2, FMGMC_PROF_KL = 3,
+       FMGMC_PROF_SMALL = 4, FMGMC_PROF_KINDS = 5 };
+int fmgmc_profile_enable(fmgmc_ctx *ctx, int32_t enable);
+int fmgmc_profile_read(fmgmc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *alg);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *fmgmc_last_error(void);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int fmgmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMGMC_H */

@@ -1,0 +1,197 @@
+// Karhunen-Loeve synthesis of the log-permeability (Section 3.1 (2)) as a
+// dense contraction over modes, on the matrix cores of gfx950:
+//   g[s][c] = sum_m xi[s][m] * B[m][c],
+//   B[m][c] = sqrt(lambda_m) phi_{a_m}(x_i) phi_{b_m}(y_j),  c = j n + i,
+//   K = exp(g) at the cell lower-left corners (x_i, y_j) = (i/n, j/n).
+// B is never stored in HBM: each workgroup builds its 64-mode x 64-cell slice
+// of it in LDS from the 1-D eigenfunction tables. The epilogue applies exp
+// and writes every level of the injected coefficient pyramid
+// (Section 2.5, Coarsening): cell (i, j) of the fine grid also serves as cell
+// (i/2^k, j/2^k) of level k whenever 2^k divides both i and j.
+#include "common.h"
+
+namespace fmgmc {
+
+namespace {
+
+constexpr int TS = 64;     // samples per tile
+constexpr int TC = 64;     // cells per tile
+constexpr int TM = 64;     // modes per LDS chunk
+constexpr int PAD = 1;     // LDS row padding (bank spread)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// epilogue shared by all precisions: value g for (sample, cell)
+__device__ __forceinline__ void store_pyramid(const KLArgs &A, int S, int s, int c, double g, bool f32exp) {
+    if (s >= S) return;
+    const int n = A.n;
+    if (c >= n * n) return;
+    const int i = c % n, j = c / n;
+    const double kv = f32exp ? double(__expf(float(g))) : exp(g);
+    int nl = n, ii = i, jj = j;
+    for (int k = 0; k < A.nlev; ++k) {
+        const size_t o = size_t(s) * nl * nl + size_t(jj) * nl + ii;
+        if (A.K64[k]) A.K64[k][o] = kv;
+        if (A.K32[k]) A.K32[k][o] = float(kv);
+        if ((ii & 1) || (jj & 1)) break;
+        ii >>= 1;
+        jj >>= 1;
+        nl >>= 1;
+    }
+}
+
+// B slice for modes [m0, m0+TM) and cells [c0, c0+TC): Bt[m][c]
+template <typename TB>
+__device__ __forceinline__ void build_b(const KLArgs &A, int m0, int c0, TB *Bt) {
+    const int n = A.n;
+    for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
+        const int mm = e / TC, cc = e % TC;
+        const int m = m0 + mm, c = c0 + cc;
+        double v = 0.0;
+        if (m < A.M && c < n * n) {
+            const int i = c % n, j = c / n;
+            v = A.sqrtlam[m] * A.phi[size_t(A.ma[m]) * n + i] * A.phi[size_t(A.mb[m]) * n + j];
+        }
+        Bt[mm * (TC + PAD) + cc] = TB(v);
+    }
+}
+
+template <typename TA>
+__device__ __forceinline__ void load_xi(const KLArgs &A, int S, int s0, int m0, TA *Xs) {
+    for (int e = threadIdx.x; e < TS * TM; e += blockDim.x) {
+        const int ss = e / TM, mm = e % TM;
+        const int s = s0 + ss, m = m0 + mm;
+        const double v = (s < S && m < A.M) ? A.xi[size_t(s) * A.M + m] : 0.0;
+        Xs[ss * (TM + PAD) + mm] = TA(v);
+    }
+}
+
+// FP64: v_mfma_f64_16x16x4_f64. Lane l: A[row l%16][k l/16], B[k l/16][col l%16];
+// output register v of lane l holds row 4 v + l/16, column l%16 (one row per
+// 16-lane group per register, unlike the FP32/BF16 16x16 forms).
+__global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
+    __shared__ double Xs[TS * (TM + PAD)];
+    __shared__ double Bt[TM * (TC + PAD)];
+    const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    d4 acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < A.M; m0 += TM) {
+        __syncthreads();
+        load_xi(A, S, s0, m0, Xs);
+        build_b(A, m0, c0, Bt);
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < TM / 4; ++kk) {
+            const double a = Xs[(16 * w + (l & 15)) * (TM + PAD) + 4 * kk + (l >> 4)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double b = Bt[(4 * kk + (l >> 4)) * (TC + PAD) + 16 * q + (l & 15)];
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            store_pyramid(A, S, s0 + 16 * w + 4 * v + (l >> 4), c0 + 16 * q + (l & 15), acc[q][v], false);
+}
+
+// FP32: v_mfma_f32_16x16x4_f32, same operand layout as the FP64 form; output
+// register v of lane l holds row 4 (l/16) + v, column l%16.
+__global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
+    __shared__ float Xs[TS * (TM + PAD)];
+    __shared__ float Bt[TM * (TC + PAD)];
+    const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    f4 acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int m0 = 0; m0 < A.M; m0 += TM) {
+        __syncthreads();
+        load_xi(A, S, s0, m0, Xs);
+        build_b(A, m0, c0, Bt);
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < TM / 4; ++kk) {
+            const float a = Xs[(16 * w + (l & 15)) * (TM + PAD) + 4 * kk + (l >> 4)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float b = Bt[(4 * kk + (l >> 4)) * (TC + PAD) + 16 * q + (l & 15)];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            store_pyramid(A, S, s0 + 16 * w + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), double(acc[q][v]), true);
+}
+
+// BF16 inputs, FP32 accumulation: v_mfma_f32_16x16x32_bf16. Lane l holds
+// A[row l%16][k = 8 (l/16) .. +7] and B[k = 8 (l/16) .. +7][col l%16]; D as above.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void k_kl_bf16(KLArgs A, int S) {
+    __shared__ __bf16 Xs[TS * (TM + 8)];
+    __shared__ __bf16 Bt[TC * (TM + 8)];   // transposed: [cell][mode]
+    const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    f4 acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    const int n = A.n;
+    for (int m0 = 0; m0 < A.M; m0 += TM) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < TS * TM; e += blockDim.x) {
+            const int ss = e / TM, mm = e % TM, s = s0 + ss, m = m0 + mm;
+            const double v = (s < S && m < A.M) ? A.xi[size_t(s) * A.M + m] : 0.0;
+            Xs[ss * (TM + 8) + mm] = __bf16(float(v));
+        }
+        for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
+            const int mm = e / TC, cc = e % TC, m = m0 + mm, c = c0 + cc;
+            double v = 0.0;
+            if (m < A.M && c < n * n)
+                v = A.sqrtlam[m] * A.phi[size_t(A.ma[m]) * n + (c % n)] * A.phi[size_t(A.mb[m]) * n + (c / n)];
+            Bt[cc * (TM + 8) + mm] = __bf16(float(v));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TM / 32; ++kk) {
+            bf8 a, b;
+            const __bf16 *pa = Xs + (16 * w + (l & 15)) * (TM + 8) + 32 * kk + 8 * (l >> 4);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] = pa[e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const __bf16 *pb = Bt + (16 * q + (l & 15)) * (TM + 8) + 32 * kk + 8 * (l >> 4);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) b[e] = pb[e];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            store_pyramid(A, S, s0 + 16 * w + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), double(acc[q][v]), true);
+}
+
+}  // namespace
+
+int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st) {
+    if (S <= 0) return FMGMC_OK;
+    dim3 grid((a.n * a.n + TC - 1) / TC, (S + TS - 1) / TS), block(256);
+    if (prec == FMGMC_KL_FP64) hipLaunchKernelGGL(k_kl_f64, grid, block, 0, st, a, S);
+    else if (prec == FMGMC_KL_FP32) hipLaunchKernelGGL(k_kl_f32, grid, block, 0, st, a, S);
+    else if (prec == FMGMC_KL_BF16) hipLaunchKernelGGL(k_kl_bf16, grid, block, 0, st, a, S);
+    else {
+        set_error("launch_kl: unknown precision");
+        return FMGMC_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+}  // namespace fmgmc

@@ -1,0 +1,281 @@
+// FP64 iterative refinement around FP32 V-cycles, FMG interpolation into
+// FP64, right-hand-side norms, per-sample convergence bookkeeping and the
+// compensated estimator reductions (Section 2.1 Eqs. (3)-(5), Section 2.4).
+#include <cmath>
+
+#include "common.h"
+
+namespace fmgmc {
+
+namespace {
+
+__device__ __forceinline__ double harm_d(double a, double b) { return 2.0 * a * b / (a + b); }
+
+template <typename T>
+__device__ __forceinline__ double ghost_d(const T *c, int nc, int I, int J, double gW, double gE) {
+    J = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
+    if (I < 0) return 2.0 * gW - double(c[J * nc]);
+    if (I >= nc) return 2.0 * gE - double(c[J * nc + nc - 1]);
+    return double(c[J * nc + I]);
+}
+
+// Refinement pass, marching over rows (one workgroup per sample, one lane per
+// column): p <- p + e; r = b - A p in FP64 with the stage operator; r is
+// handed to the next FP32 cycles, ||r||^2 and the east outflow accumulate.
+__global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
+    const int n = A.n, i = threadIdx.x, s = blockIdx.x;
+    if (A.active && A.active[s] == 0) return;
+    extern __shared__ unsigned char smem_raw[];
+    double *ps = reinterpret_cast<double *>(smem_raw);  // [3][n]
+    double *ks = ps + 3 * n;                            // [3][n]
+    double *red = ks + 3 * n;                           // [16]
+    const size_t base = size_t(s) * n * n;
+    double rr = 0.0, q = 0.0;
+    double tn_prev = 0.0;
+    for (int F = 0; F <= n; ++F) {
+        if (F < n) {
+            const size_t idx = base + size_t(F) * n + i;
+            double pv = A.p[idx];
+            if (A.e) pv += double(A.e[idx]);
+            ps[(F % 3) * n + i] = pv;
+            ks[(F % 3) * n + i] = A.K[idx];
+        }
+        __syncthreads();
+        const int r = F - 1;
+        if (r >= 0) {
+            const double *kr = ks + (r % 3) * n, *pr = ps + (r % 3) * n;
+            const double k0 = kr[i], x0 = pr[i];
+            const double tw = (i > 0) ? harm_d(kr[i - 1], k0) : 2.0 * k0;
+            const double te = (i < n - 1) ? harm_d(k0, kr[i + 1]) : 2.0 * k0;
+            const double tn = (r + 1 < n) ? harm_d(k0, ks[(F % 3) * n + i]) : 0.0;
+            const double ts = tn_prev;
+            double acc = 0.0;
+            if (i == 0) acc += tw * A.pW;
+            if (i == n - 1) acc += te * A.pE;
+            if (i > 0) acc += tw * pr[i - 1];
+            if (i < n - 1) acc += te * pr[i + 1];
+            if (r > 0) acc += ts * ps[((r + 2) % 3) * n + i];
+            if (r + 1 < n) acc += tn * ps[(F % 3) * n + i];
+            const double res = acc - (((tw + te) + ts) + tn) * x0;
+            rr += res * res;
+            A.r32[base + size_t(r) * n + i] = float(res);
+            if (A.e) A.p[base + size_t(r) * n + i] = x0;
+            if (i == n - 1) q += te * (x0 - A.pE);
+            tn_prev = tn;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
+    __syncthreads();
+    if ((i & 63) == 0) red[i >> 6] = rr;
+    __syncthreads();
+    if (i == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (n + 63) / 64; ++w) t += red[w];
+        A.rr[s] = t;
+    }
+    if (i == n - 1) A.q[s] = q;
+}
+
+template <typename TS>
+__global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE) {
+    const int s = blockIdx.y;
+    if (active && active[s] == 0) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n * n) return;
+    const int i = c % n, j = c / n, nc = n / 2;
+    const TS *x = xc + size_t(s) * nc * nc;
+    const int I = i >> 1, J = j >> 1, di = (i & 1) ? 1 : -1, dj = (j & 1) ? 1 : -1;
+    p[size_t(s) * n * n + c] =
+        (9.0 * ghost_d(x, nc, I, J, pW, pE) + 3.0 * ghost_d(x, nc, I + di, J, pW, pE) +
+         3.0 * ghost_d(x, nc, I, J + dj, pW, pE) + ghost_d(x, nc, I + di, J + dj, pW, pE)) / 16.0;
+}
+
+template <typename T>
+__global__ void k_bnorm(int n, const T *K, double pW, double pE, double *bn, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const T *k = K + size_t(s) * n * n;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double bw = 2.0 * double(k[size_t(j) * n]) * pW;
+        const double be = 2.0 * double(k[size_t(j) * n + n - 1]) * pE;
+        acc += bw * bw + be * be;
+    }
+    bn[s] = sqrt(acc);
+}
+
+__global__ __launch_bounds__(1024) void k_check(CheckArgs A, int S) {
+    __shared__ int cnt[16];
+    int mine = 0;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        if (A.active[s] == 0) continue;
+        const int cyc = (A.cycles[2 * s + A.slot] += A.inc);
+        const double rel = sqrt(A.rr[s]) / A.bnorm[s];
+        bool stop = false;
+        if (!isfinite(rel)) {
+            A.flags[s] |= FMGMC_FLAG_NONFINITE;
+            stop = true;
+        } else if (rel <= A.tol) {
+            stop = true;
+        } else if (A.inc > 0 && cyc >= A.max_cycles) {
+            A.flags[s] |= FMGMC_FLAG_NOTCONV;
+            stop = true;
+        }
+        if (stop) {
+            A.active[s] = 0;
+            A.qout[s] = A.q[s];
+        } else {
+            ++mine;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) t += cnt[w];
+        A.n_active[0] = t;
+    }
+}
+
+template <typename V>
+__global__ void k_fill(V *p, V v, int64_t n) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// ---- compensated sums: each lane sums a contiguous chunk in order (Neumaier),
+// then the lanes' (sum, compensation) pairs are combined in a fixed tree.
+struct NS {
+    double s, c;
+};
+__device__ __forceinline__ void nadd(NS &a, double x) {
+    const double t = a.s + x;
+    a.c += (fabs(a.s) >= fabs(x)) ? (a.s - t) + x : (x - t) + a.s;
+    a.s = t;
+}
+__device__ __forceinline__ NS ncomb(NS a, NS b) {
+    nadd(a, b.s);
+    a.c += b.c;
+    return a;
+}
+
+constexpr int RT = 256;
+
+template <typename Fn>
+__device__ double block_nsum(int64_t n, Fn val, NS *sh) {
+    const int64_t chunk = (n + RT - 1) / RT;
+    const int64_t lo = threadIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    NS a{0.0, 0.0};
+    for (int64_t k = lo; k < hi; ++k) nadd(a, val(k));
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = RT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = ncomb(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double r = sh[0].s + sh[0].c;
+    __syncthreads();
+    return r;
+}
+
+// out: [mean_y, var_y, mean_qf, var_qf, mean_qc]; RQMC (nshift > 1): var_y is the
+// variance of the estimate from the per-shift means, shift means in scratch.
+__global__ __launch_bounds__(RT) void k_level_reduce(const double *qf, const double *qc, int64_t n, int nshift,
+                                                     double *out, double *shift_means) {
+    __shared__ NS sh[RT];
+    if (nshift <= 1) {
+        const double my = block_nsum(n, [&](int64_t k) { return qf[k] - qc[k]; }, sh) / double(n);
+        const double mf = block_nsum(n, [&](int64_t k) { return qf[k]; }, sh) / double(n);
+        const double mc = block_nsum(n, [&](int64_t k) { return qc[k]; }, sh) / double(n);
+        const double vy = n > 1 ? block_nsum(n, [&](int64_t k) { const double d = (qf[k] - qc[k]) - my; return d * d; }, sh) / double(n - 1) : 0.0;
+        const double vf = n > 1 ? block_nsum(n, [&](int64_t k) { const double d = qf[k] - mf; return d * d; }, sh) / double(n - 1) : 0.0;
+        if (threadIdx.x == 0) {
+            out[0] = my; out[1] = vy; out[2] = mf; out[3] = vf; out[4] = mc;
+        }
+        return;
+    }
+    const int64_t np = n / nshift;
+    for (int r = 0; r < nshift; ++r) {
+        const double *f = qf + size_t(r) * np, *c = qc + size_t(r) * np;
+        const double m = block_nsum(np, [&](int64_t k) { return f[k] - c[k]; }, sh) / double(np);
+        if (threadIdx.x == 0) shift_means[r] = m;
+    }
+    __syncthreads();
+    const double m = block_nsum(nshift, [&](int64_t k) { return shift_means[k]; }, sh) / double(nshift);
+    const double v = block_nsum(nshift, [&](int64_t k) { const double d = shift_means[k] - m; return d * d; }, sh) /
+                     (double(nshift) * double(nshift - 1));
+    const double mf = block_nsum(n, [&](int64_t k) { return qf[k]; }, sh) / double(n);
+    const double mc = block_nsum(n, [&](int64_t k) { return qc[k]; }, sh) / double(n);
+    const double vf = n > 1 ? block_nsum(n, [&](int64_t k) { const double d = qf[k] - mf; return d * d; }, sh) / double(n - 1) : 0.0;
+    if (threadIdx.x == 0) {
+        out[0] = m; out[1] = v; out[2] = mf; out[3] = vf; out[4] = mc;
+    }
+}
+
+}  // namespace
+
+int launch_ir(const IRArgs &a, int S, hipStream_t st) {
+    if (a.n < 8 || a.n > 1024) {
+        set_error("launch_ir: n out of range");
+        return FMGMC_EINVAL;
+    }
+    if (S <= 0) return FMGMC_OK;
+    const size_t lds = (6 * size_t(a.n) + 16) * sizeof(double);
+    hipLaunchKernelGGL(k_ir, dim3(S), dim3(a.n), lds, st, a);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+template <typename TS>
+int launch_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE, int S,
+                    hipStream_t st) {
+    if (S <= 0) return FMGMC_OK;
+    dim3 grid((n * n + 255) / 256, S);
+    hipLaunchKernelGGL(k_interp64<TS>, grid, dim3(256), 0, st, n, xc, p, active, pW, pE);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+template int launch_interp64<float>(int, const float *, double *, const int32_t *, double, double, int, hipStream_t);
+template int launch_interp64<double>(int, const double *, double *, const int32_t *, double, double, int, hipStream_t);
+
+template <typename T>
+int launch_bnorm(int n, const T *K, double pW, double pE, double *bn, int S, hipStream_t st) {
+    if (S <= 0) return FMGMC_OK;
+    hipLaunchKernelGGL(k_bnorm<T>, dim3((S + 255) / 256), dim3(256), 0, st, n, K, pW, pE, bn, S);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+template int launch_bnorm<double>(int, const double *, double, double, double *, int, hipStream_t);
+template int launch_bnorm<float>(int, const float *, double, double, double *, int, hipStream_t);
+
+int launch_check(const CheckArgs &a, int S, hipStream_t st) {
+    if (S <= 0) return FMGMC_OK;
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(1024), 0, st, a, S);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+int launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return FMGMC_OK;
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+int launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return FMGMC_OK;
+    hipLaunchKernelGGL(k_fill<uint8_t>, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+int launch_fill_f64(double *p, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return FMGMC_OK;
+    hipLaunchKernelGGL(k_fill<double>, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+int launch_level_reduce(const double *qf, const double *qc, int64_t n, int nshift, double *out, double *scratch,
+                        hipStream_t st) {
+    if (n <= 0 || nshift < 1 || (nshift > 1 && n % nshift != 0)) {
+        set_error("launch_level_reduce: bad sizes");
+        return FMGMC_EINVAL;
+    }
+    hipLaunchKernelGGL(k_level_reduce, dim3(1), dim3(RT), 0, st, qf, qc, n, nshift, out, scratch);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+}  // namespace fmgmc

@@ -1,0 +1,314 @@
+// Small grids (n <= 32): one workgroup holds a sample's whole sub-hierarchy
+// in LDS and runs a complete V(nu1,nu2) cycle: red-black Gauss-Seidel,
+// residual restriction by 2x2 sums, bilinear prolongation, and the direct
+// solve on the coarsest grid (Section 2.5; Cholesky factor precomputed in
+// FP64). With top == 0 the call is the coarsest-grid direct solve itself
+// (the first stage of full multigrid).
+#include "common.h"
+
+namespace fmgmc {
+
+namespace {
+
+constexpr int kMaxLev = 4;   // 4, 8, 16, 32
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ T harm_s(T a, T b) {
+    return T(2) * a * b / (a + b);
+}
+
+template <typename T>
+struct Lv {
+    int n;
+    T *x, *b, *fx, *fy, *fxe, *id;
+};
+
+template <typename T>
+__device__ __forceinline__ T ghost_at(const T *c, int nc, int I, int J, T gW, T gE) {
+    J = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
+    if (I < 0) return T(2) * gW - c[J * nc];
+    if (I >= nc) return T(2) * gE - c[J * nc + nc - 1];
+    return c[J * nc + I];
+}
+
+template <typename T>
+__device__ __forceinline__ T interp_at(const T *c, int nc, int i, int j, T gW, T gE) {
+    const int I = i >> 1, J = j >> 1;
+    const int di = (i & 1) ? 1 : -1, dj = (j & 1) ? 1 : -1;
+    return (T(9) * ghost_at(c, nc, I, J, gW, gE) + T(3) * ghost_at(c, nc, I + di, J, gW, gE) +
+            T(3) * ghost_at(c, nc, I, J + dj, gW, gE) + ghost_at(c, nc, I + di, J + dj, gW, gE)) /
+           T(16);
+}
+
+// sum over interior neighbours of T_nb x_nb, plus b
+template <typename T>
+__device__ __forceinline__ T nbsum(const Lv<T> &L, int i, int j) {
+    const int n = L.n, P = j * n + i;
+    T acc = L.b[P];
+    if (i > 0) acc += L.fx[P] * L.x[P - 1];
+    if (i < n - 1) acc += L.fx[P + 1] * L.x[P + 1];
+    if (j > 0) acc += L.fy[P] * L.x[P - n];
+    if (j < n - 1) acc += L.fy[P + n] * L.x[P + n];
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T diag(const Lv<T> &L, int i, int j) {
+    const int n = L.n, P = j * n + i;
+    const T te = (i < n - 1) ? L.fx[P + 1] : L.fxe[j];
+    const T tn = (j < n - 1) ? L.fy[P + n] : T(0);
+    return ((L.fx[P] + te) + L.fy[P]) + tn;
+}
+
+template <typename T>
+__device__ void half_sweep(const Lv<T> &L, int colour) {
+    const int n = L.n, h = n >> 1;
+    for (int c = threadIdx.x; c < n * h; c += blockDim.x) {
+        const int j = c / h, i = 2 * (c % h) + ((j + colour) & 1);
+        L.x[j * n + i] = nbsum(L, i, j) * L.id[j * n + i];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void smooth(const Lv<T> &L, int nu) {
+    for (int k = 0; k < nu; ++k) {
+        half_sweep(L, 0);
+        half_sweep(L, 1);
+    }
+}
+
+template <typename T>
+__device__ void chol_solve16(const double *Ls, int N, const T *b, T *x, double *y) {
+    // one thread: forward and back substitution in FP64
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < N; ++r) {
+            double s = double(b[r]);
+            for (int k = 0; k < r; ++k) s -= Ls[r * N + k] * y[k];
+            y[r] = s / Ls[r * N + r];
+        }
+        for (int r = N - 1; r >= 0; --r) {
+            double s = y[r];
+            for (int k = r + 1; k < N; ++k) s -= Ls[k * N + r] * y[k];
+            y[r] = s / Ls[r * N + r];
+        }
+        for (int r = 0; r < N; ++r) x[r] = T(y[r]);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bool rhs_array, int out) {
+    const int s = blockIdx.x;
+    if (A.active && A.active[s] == 0) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *p = reinterpret_cast<T *>(smem_raw);
+    Lv<T> L[kMaxLev];
+    const int top = A.top;
+    for (int k = 0; k <= top; ++k) {
+        const int n = A.ns[k];
+        L[k].n = n;
+        L[k].x = p; p += n * n;
+        L[k].b = p; p += n * n;
+        L[k].fx = p; p += n * n;
+        L[k].fy = p; p += n * n;
+        L[k].id = p; p += n * n;
+        L[k].fxe = p; p += n;
+    }
+    double *Ls = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(p) + 7) & ~uintptr_t(7));
+    const int N0 = A.ns[0] * A.ns[0];
+    double *y = Ls + N0 * N0;
+    T *red = reinterpret_cast<T *>(y + N0);
+    const T gW = T(A.pW), gE = T(A.pE);
+
+    // coefficients of every level
+    for (int k = 0; k <= top; ++k) {
+        const int n = L[k].n, nn = n * n;
+        if (k == top && A.top_from_k) {
+            const T *K = A.Ktop + size_t(s) * nn;
+            for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+                const int i = c % n, j = c / n;
+                L[k].fx[c] = i == 0 ? T(2) * K[c] : harm_s(K[c - 1], K[c]);
+                L[k].fy[c] = j == 0 ? T(0) : harm_s(K[c - n], K[c]);
+                if (i == n - 1) L[k].fxe[j] = T(2) * K[c];
+            }
+        } else {
+            const Faces<T> f = A.f[k];
+            for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+                L[k].fx[c] = f.fx[size_t(s) * nn + c];
+                L[k].fy[c] = f.fy[size_t(s) * nn + c];
+            }
+            for (int c = threadIdx.x; c < n; c += blockDim.x) L[k].fxe[c] = f.fxe[size_t(s) * n + c];
+        }
+    }
+    for (int c = threadIdx.x; c < N0 * N0; c += blockDim.x) Ls[c] = A.chol[size_t(s) * N0 * N0 + c];
+    __syncthreads();
+    for (int k = 0; k <= top; ++k) {
+        const int n = L[k].n;
+        for (int c = threadIdx.x; c < n * n; c += blockDim.x)
+            L[k].id[c] = T(1) / diag(L[k], c % n, c / n);
+    }
+    // right-hand side and initial guess on the top level
+    {
+        Lv<T> &Tp = L[top];
+        const int n = Tp.n, nn = n * n;
+        for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+            const int i = c % n, j = c / n;
+            if (rhs_array) {
+                Tp.b[c] = A.b[size_t(s) * nn + c];
+            } else {
+                T b0 = T(0);
+                if (i == 0) b0 += Tp.fx[c] * gW;
+                if (i == n - 1) b0 += Tp.fxe[j] * gE;
+                Tp.b[c] = b0;
+            }
+            T xv = T(0);
+            if (init == INIT_LOAD) xv = A.x[size_t(s) * nn + c];
+            else if (init == INIT_INTERP) xv = interp_at(A.xc + size_t(s) * (nn / 4), n / 2, i, j, gW, gE);
+            Tp.x[c] = xv;
+        }
+    }
+    __syncthreads();
+
+    // V-cycle: descend
+    for (int k = top; k >= 1; --k) {
+        smooth(L[k], A.nu1);
+        const int n = L[k].n, nc = n / 2;
+        for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
+            const int I = c % nc, J = c / nc;
+            T acc = T(0);
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int i = 2 * I + di, j = 2 * J + dj;
+                    acc += nbsum(L[k], i, j) - diag(L[k], i, j) * L[k].x[j * n + i];
+                }
+            L[k - 1].b[c] = acc;
+            L[k - 1].x[c] = T(0);
+        }
+        __syncthreads();
+    }
+    chol_solve16(Ls, N0, L[0].b, L[0].x, y);
+    // ascend
+    for (int k = 1; k <= top; ++k) {
+        const int n = L[k].n, nc = n / 2;
+        for (int c = threadIdx.x; c < n * n; c += blockDim.x)
+            L[k].x[c] += interp_at(L[k - 1].x, nc, c % n, c / n, T(0), T(0));
+        __syncthreads();
+        smooth(L[k], A.nu2);
+    }
+
+    // outputs
+    Lv<T> &Tp = L[top];
+    const int n = Tp.n, nn = n * n;
+    for (int c = threadIdx.x; c < nn; c += blockDim.x) A.x[size_t(s) * nn + c] = Tp.x[c];
+    if (out & OUT_RR) {
+        T rr = T(0);
+        for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+            const int i = c % n, j = c / n;
+            const T r = nbsum(Tp, i, j) - diag(Tp, i, j) * Tp.x[c];
+            rr += r * r;
+        }
+        for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T t = T(0);
+            for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+            A.rr[s] = double(t);
+        }
+    }
+    if ((out & OUT_Q) && threadIdx.x == 0) {
+        T q = T(0);
+        for (int j = 0; j < n; ++j) q += Tp.fxe[j] * (Tp.x[j * n + n - 1] - gE);
+        A.q[s] = double(q);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out, hipStream_t st) {
+    if (a.top < 0 || a.top >= kMaxLev || a.ns[0] * a.ns[0] > 64) {
+        set_error("launch_small: unsupported hierarchy");
+        return FMGMC_EINVAL;
+    }
+    if (S <= 0) return FMGMC_OK;
+    size_t words = 0;
+    for (int k = 0; k <= a.top; ++k) words += 5 * size_t(a.ns[k]) * a.ns[k] + a.ns[k];
+    const int N0 = a.ns[0] * a.ns[0];
+    size_t bytes = words * sizeof(T);
+    bytes = (bytes + 7) & ~size_t(7);
+    bytes += (size_t(N0) * N0 + N0) * sizeof(double) + 8 * sizeof(T);
+    hipLaunchKernelGGL(k_small<T>, dim3(S), dim3(kThreads), bytes, st, a, init, rhs_array, out);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+template int launch_small<double>(const SmallArgs<double> &, int, int, bool, int, hipStream_t);
+template int launch_small<float>(const SmallArgs<float> &, int, int, bool, int, hipStream_t);
+
+// --------------------------------------------------------- coarsest factor
+template <typename T>
+__global__ void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout, int S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const int N = n0 * n0;
+    double *L = Lout + size_t(s) * N * N;
+    auto fxv = [&](int i, int j) -> double {
+        if (from_k) {
+            const T *k = K + size_t(s) * N;
+            return i == 0 ? 2.0 * double(k[j * n0]) : double(harm_s(k[j * n0 + i - 1], k[j * n0 + i]));
+        }
+        return double(f.fx[size_t(s) * N + j * n0 + i]);
+    };
+    auto fxe = [&](int j) -> double {
+        if (from_k) return 2.0 * double(K[size_t(s) * N + j * n0 + n0 - 1]);
+        return double(f.fxe[size_t(s) * n0 + j]);
+    };
+    auto fyv = [&](int i, int j) -> double {
+        if (j == 0) return 0.0;
+        if (from_k) {
+            const T *k = K + size_t(s) * N;
+            return double(harm_s(k[(j - 1) * n0 + i], k[j * n0 + i]));
+        }
+        return double(f.fy[size_t(s) * N + j * n0 + i]);
+    };
+    for (int c = 0; c < N * N; ++c) L[c] = 0.0;
+    for (int j = 0; j < n0; ++j)
+        for (int i = 0; i < n0; ++i) {
+            const int P = j * n0 + i;
+            const double w = fxv(i, j), e = (i < n0 - 1) ? fxv(i + 1, j) : fxe(j);
+            const double so = fyv(i, j), no = (j < n0 - 1) ? fyv(i, j + 1) : 0.0;
+            L[P * N + P] = ((w + e) + so) + no;
+            if (i > 0) L[P * N + P - 1] = -w;
+            if (j > 0) L[P * N + P - n0] = -so;
+        }
+    // in-place lower Cholesky (only the lower triangle is referenced)
+    for (int c = 0; c < N; ++c) {
+        double d = L[c * N + c];
+        for (int k = 0; k < c; ++k) d -= L[c * N + k] * L[c * N + k];
+        d = sqrt(d);  // NaN for a non-SPD (non-finite) operator; flagged by the residual check
+        L[c * N + c] = d;
+        for (int r = c + 1; r < N; ++r) {
+            double v = L[r * N + c];
+            for (int k = 0; k < c; ++k) v -= L[r * N + k] * L[c * N + k];
+            L[r * N + c] = v / d;
+        }
+    }
+}
+
+template <typename T>
+int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, double *L, int S, hipStream_t st) {
+    if (n0 * n0 > 64) {
+        set_error("launch_chol: coarsest grid too large");
+        return FMGMC_EINVAL;
+    }
+    if (S <= 0) return FMGMC_OK;
+    hipLaunchKernelGGL(k_chol<T>, dim3((S + 63) / 64), dim3(64), 0, st, n0, K, f, from_k, L, S);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+template int launch_chol<double>(int, const double *, Faces<double>, bool, double *, int, hipStream_t);
+template int launch_chol<float>(int, const float *, Faces<float>, bool, double *, int, hipStream_t);
+
+}  // namespace fmgmc

@@ -1,0 +1,224 @@
+"""Thin ctypes binding of the C ABI in include/fmgmc.h (argument marshalling only).
+
+Every step of the method runs in the HIP library libfmgmc.so; this module only
+converts arguments. Arrays may be torch tensors (device or host) or numpy
+arrays (host). If the library has not been built the import of this module
+succeeds but every call raises: there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmgmc.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
+FLAG_NOTCONV, FLAG_NONFINITE = 1, 2
+SOLVERS = {"fp64": 0, "fp32_ir": 1}
+KL_PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class Field(C.Structure):
+    _fields_ = [("sigma2", C.c_double), ("corr_len", C.c_double), ("n_modes", C.c_int32),
+                ("cov_kind", C.c_int32)]
+
+
+class Hier(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n0", C.c_int32), ("n_coarsest", C.c_int32),
+                ("reserved", C.c_int32), ("p_west", C.c_double), ("p_east", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("kl_prec", C.c_int32), ("nu1", C.c_int32),
+                ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("inner_cycles", C.c_int32),
+                ("max_batch", C.c_int32), ("reserved", C.c_int32), ("rel_tol", C.c_double)]
+
+
+class LevelEst(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean_y", C.c_double), ("var_y", C.c_double),
+                ("mean_qf", C.c_double), ("var_qf", C.c_double), ("mean_qc", C.c_double)]
+
+
+class FmgmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fmgmc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_VP = C.c_void_p
+_SIGS = {
+    "fmgmc_create": (C.c_int, [C.POINTER(_VP), C.POINTER(Field), C.POINTER(Hier), C.POINTER(Opts), C.c_int]),
+    "fmgmc_destroy": (C.c_int, [_VP]),
+    "fmgmc_mode_table": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32]),
+    "fmgmc_kl_modes": (C.c_int, [C.c_double, C.c_double, C.c_int32, _VP, _VP, _VP]),
+    "fmgmc_synthesize_field": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP]),
+    "fmgmc_solve_level": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "fmgmc_estimate": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "fmgmc_profile_enable": (C.c_int, [_VP, C.c_int32]),
+    "fmgmc_profile_read": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
+    "fmgmc_last_error": (C.c_char_p, []),
+    "fmgmc_version": (C.c_int, []),
+}
+
+
+def lib():
+    """Loads libfmgmc.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FmgmcError(EINVAL, f"{LIB_PATH} is missing: build it with paper_1910_04727_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().fmgmc_last_error().decode()
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise FmgmcError(rc, last_error())
+    return rc
+
+
+def _ptr(a):
+    """Raw pointer of a torch tensor or numpy array (must be contiguous)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr()
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+def kl_modes(sigma2, corr_len, n_modes):
+    """Host-only KL mode table: (a, b, lambda) numpy arrays."""
+    a = np.zeros(n_modes, np.int32)
+    b = np.zeros(n_modes, np.int32)
+    lam = np.zeros(n_modes)
+    _check(lib().fmgmc_kl_modes(sigma2, corr_len, n_modes, _ptr(a), _ptr(b), _ptr(lam)))
+    return a, b, lam
+
+
+class Context:
+    """One library context (field, level hierarchy, solver options) on one device."""
+
+    def __init__(self, sigma2, corr_len, n_modes, n_levels, n0, solver="fp64", kl_prec="fp64",
+                 nu1=2, nu2=2, max_cycles=50, inner_cycles=1, max_batch=0, rel_tol=1e-10,
+                 p_west=1.0, p_east=0.0, device=0):
+        self.field = Field(sigma2, corr_len, n_modes, 0)
+        self.hier = Hier(n_levels, n0, 4, 0, p_west, p_east)
+        self.opts = Opts(SOLVERS[solver], KL_PREC[kl_prec], nu1, nu2, max_cycles, inner_cycles,
+                         max_batch, 0, rel_tol)
+        self.n_modes = n_modes
+        self.n0 = n0
+        self.n_levels = n_levels
+        h = _VP()
+        _check(lib().fmgmc_create(C.byref(h), C.byref(self.field), C.byref(self.hier),
+                                  C.byref(self.opts), device))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fmgmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    PROF_KINDS = ("pre", "post", "ir", "kl", "small")
+
+    def profile(self, enable=True):
+        _check(lib().fmgmc_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kind: (ms, launches, algorithmic bytes or flops)}; clears the records."""
+        out = {}
+        for k, name in enumerate(self.PROF_KINDS):
+            ms = C.c_double()
+            cnt = C.c_int64()
+            alg = C.c_double()
+            _check(lib().fmgmc_profile_read(self._h, k, C.byref(ms), C.byref(cnt), C.byref(alg)))
+            out[name] = (ms.value, cnt.value, alg.value)
+        return out
+
+    def grid(self, level):
+        return self.n0 << level
+
+    def mode_table(self):
+        a = np.zeros(self.n_modes, np.int32)
+        b = np.zeros(self.n_modes, np.int32)
+        lam = np.zeros(self.n_modes)
+        m = _check_count(lib().fmgmc_mode_table(self._h, _ptr(a), _ptr(b), _ptr(lam), self.n_modes))
+        return a[:m], b[:m], lam[:m]
+
+    def synthesize_field(self, level, xi, out, stream=None):
+        ns = xi.shape[0]
+        _check(lib().fmgmc_synthesize_field(self._h, level, ns, _ptr(xi), _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def solve_level(self, level, xi, q_fine, q_coarse, cycles=None, flags=None, stream=None,
+                    allow=(ENOTCONV, ENONFINITE)):
+        """Returns the library's status code (OK / ENOTCONV / ENONFINITE); raises on others."""
+        ns = xi.shape[0]
+        rc = lib().fmgmc_solve_level(self._h, level, ns, _ptr(xi), _ptr(q_fine), _ptr(q_coarse),
+                                     _ptr(cycles), _ptr(flags), _stream_ptr(stream))
+        return _check(rc, allow)
+
+
+def _check_count(rc):
+    if rc < 0:
+        raise FmgmcError(rc, last_error())
+    return rc
+
+
+def estimate(qf_levels, qc_levels, n_shifts=1, stream=None):
+    """MLMC / MLQMC estimate over levels; arrays host or device (float64, 1-D)."""
+    L = len(qf_levels)
+    n = np.array([int(q.shape[0]) for q in qf_levels], np.int64)
+    pf = (C.c_void_p * L)(*[_ptr(q) for q in qf_levels])
+    pc = (C.c_void_p * L)(*[_ptr(q) for q in qc_levels])
+    out = (LevelEst * L)()
+    mean = C.c_double()
+    var = C.c_double()
+    _check(lib().fmgmc_estimate(L, _ptr(n), C.cast(pf, C.c_void_p), C.cast(pc, C.c_void_p), n_shifts,
+                                C.cast(out, C.c_void_p), C.byref(mean), C.byref(var), _stream_ptr(stream)))
+    levels = [dict(n=o.n, mean_y=o.mean_y, var_y=o.var_y, mean_qf=o.mean_qf, var_qf=o.var_qf,
+                   mean_qc=o.mean_qc) for o in out]
+    return dict(levels=levels, mean=mean.value, var_of_mean=var.value)
+
+
+def header_functions():
+    """Names of the functions declared in include/fmgmc.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "fmgmc.h")
+    txt = open(hdr).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(fmgmc_\w+)\s*\(", txt, re.M)))
