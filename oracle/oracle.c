@@ -31,7 +31,8 @@
  *
  * Readings where the paper is silent (all listed in the design notes):
  *   field sampled at cell lower-left corners (i h, j h); V(nu1,nu2) cycles of
- *   red-black Gauss-Seidel (red = (i+j) even, red sweep first), residual
+ *   red-black Gauss-Seidel (red = (i+j) even, red sweep first) whose
+ *   coarse-grid corrections on grids of n <= 64 are W-cycles, residual
  *   restriction by summing the four children, bilinear cell-centred
  *   prolongation, stage operators rediscretised from the injected K and
  *   V-cycle correction operators by face averaging (see section 4),
@@ -482,15 +483,23 @@ void oracle_coarsen_faces(int n, const double *Txf, const double *Tyf, double *T
                                             + Tyf[(size_t)(2 * J) * n + 2 * I + 1]);
 }
 
-/* A V-cycle context: ops[0..top], ops[top] the operator being solved. */
+/* A cycle context: ops[0..top], ops[top] the operator being solved. */
 typedef struct {
     const oop *ops;
     oscratch *s;
     const double *chol; /* Cholesky factor of ops[0] */
     int nu1, nu2;
+    int wmax;           /* coarse grids with n <= wmax are cycled twice (W-cycle) */
 } ovc;
 
-/* One V(nu1,nu2) cycle for ops[k] x = b (x updated in place). */
+/*
+ * One multigrid cycle for ops[k] x = b (x updated in place): nu1 red-black
+ * sweeps, residual restricted to the next coarser grid, coarse-grid
+ * correction from zero, bilinear prolongation, nu2 sweeps. The coarse-grid
+ * correction is itself one cycle, or two in succession when the coarse grid
+ * has n <= wmax and is not the coarsest (a W-cycle below that size, a
+ * V(nu1,nu2) cycle above it); the coarsest grid is solved directly.
+ */
 static void vcycle(const ovc *V, int k, double *x, const double *b)
 {
     const oop *A = &V->ops[k];
@@ -508,6 +517,8 @@ static void vcycle(const ovc *V, int k, double *x, const double *b)
     oracle_restrict(n, V->s[k].r, C->b);
     memset(C->x, 0, sizeof(double) * (size_t)C->n * C->n);
     vcycle(V, k - 1, C->x, C->b);
+    if (C->n <= V->wmax && k - 1 > 0)
+        vcycle(V, k - 1, C->x, C->b);
     oracle_prolong_add(C->n, C->x, x);
     for (int s = 0; s < V->nu2; ++s) {
         oracle_rbgs_half(n, A->Tx, A->Ty, b, x, 0);
@@ -541,7 +552,7 @@ static double relres(const oop *A, double *r, const double *x, const double *b)
  */
 int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fine,
                       double pW, double pE, double tol, int max_cycles, int nu1, int nu2,
-                      double *qf, double *qc, int *cycles, int *flags, double *hist)
+                      int wmax, double *qf, double *qc, int *cycles, int *flags, double *hist)
 {
     *qf = 0.0;
     *qc = 0.0;
@@ -627,6 +638,7 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
             V.chol = (k == 0) ? chol_stage : chol_pyr[q];
             V.nu1 = nu1;
             V.nu2 = nu2;
+            V.wmax = wmax;
 
             if (is_fine || is_coarse) {
                 int slot = is_fine ? 1 : 0;
@@ -686,7 +698,7 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
 int oracle_solve_level(double sigma2, double corr_len, int M, const int *a, const int *b,
                        const double *lam, int n_fine, int n_coarsest, int level,
                        int64_t ns, const double *xi, double pW, double pE, double tol,
-                       int max_cycles, int nu1, int nu2, double *qf, double *qc,
+                       int max_cycles, int nu1, int nu2, int wmax, double *qf, double *qc,
                        int *cycles, int *flags, int nthreads)
 {
     (void)sigma2;
@@ -702,7 +714,7 @@ int oracle_solve_level(double sigma2, double corr_len, int M, const int *a, cons
         double *K = (double *)malloc(sizeof(double) * (size_t)n_fine * n_fine);
         oracle_field(n_fine, corr_len, M, a, b, lam, xi + (size_t)s * M, K);
         int r = oracle_fmg_sample(n_fine, n_coarsest, level, K, pW, pE, tol, max_cycles,
-                                  nu1, nu2, &qf[s], &qc[s], &cycles[2 * s], &flags[s], NULL);
+                                  nu1, nu2, wmax, &qf[s], &qc[s], &cycles[2 * s], &flags[s], NULL);
         if (r != 0)
             err |= 1;
         free(K);

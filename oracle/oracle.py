@@ -48,10 +48,10 @@ def lib():
             "oracle_chol_factor": (_i, [_i, _pd, _pd, _pd]),
             "oracle_chol_solve": (None, [_i, _pd, _pd, _pd]),
             "oracle_coarsen_faces": (None, [_i, _pd, _pd, _pd, _pd]),
-            "oracle_fmg_sample": (_i, [_i, _i, _i, _pd, _d, _d, _d, _i, _i, _i,
+            "oracle_fmg_sample": (_i, [_i, _i, _i, _pd, _d, _d, _d, _i, _i, _i, _i,
                                        C.POINTER(_d), C.POINTER(_d), _pi, C.POINTER(_i), C.c_void_p]),
             "oracle_solve_level": (_i, [_d, _d, _i, _pi, _pi, _pd, _i, _i, _i, _i64, _pd, _d, _d,
-                                        _d, _i, _i, _i, _pd, _pd, _pi, _pi, _i]),
+                                        _d, _i, _i, _i, _i, _pd, _pd, _pi, _pi, _i]),
             "oracle_max_threads": (_i, []),
             "oracle_sum": (_d, [_i64, _pd]),
             "oracle_level_stats": (_i, [_i64, _pd, _pd, _pd]),
@@ -187,8 +187,11 @@ def chol_solve(K, b):
 
 
 # --- full multigrid ------------------------------------------------------
+W_MAX = 64  # coarse grids with n <= 64 get W-cycle (two) coarse-grid corrections
+
+
 def fmg_sample(K, level, tol=1e-10, max_cycles=50, nu1=2, nu2=2, pW=1.0, pE=0.0,
-               n_coarsest=4, history=False):
+               n_coarsest=4, history=False, wmax=W_MAX):
     """One FMG pass; returns dict(qf, qc, cycles, flags[, hist])."""
     n = K.shape[0]
     qf = C.c_double()
@@ -197,7 +200,7 @@ def fmg_sample(K, level, tol=1e-10, max_cycles=50, nu1=2, nu2=2, pW=1.0, pE=0.0,
     fl = C.c_int()
     hist = np.zeros(2 * max_cycles) if history else None
     rc = lib().oracle_fmg_sample(n, n_coarsest, level, _f64(K), pW, pE, tol, max_cycles,
-                                 nu1, nu2, C.byref(qf), C.byref(qc), cyc, C.byref(fl),
+                                 nu1, nu2, wmax, C.byref(qf), C.byref(qc), cyc, C.byref(fl),
                                  hist.ctypes.data if history else None)
     out = dict(qf=qf.value, qc=qc.value, cycles=cyc, flags=fl.value, rc=rc)
     if history:
@@ -206,7 +209,7 @@ def fmg_sample(K, level, tol=1e-10, max_cycles=50, nu1=2, nu2=2, pW=1.0, pE=0.0,
 
 
 def solve_level(sigma2, corr_len, table, n_fine, level, xi, tol=1e-10, max_cycles=50,
-                nu1=2, nu2=2, pW=1.0, pE=0.0, n_coarsest=4, nthreads=0):
+                nu1=2, nu2=2, pW=1.0, pE=0.0, n_coarsest=4, nthreads=0, wmax=W_MAX):
     """Batched oracle: xi [ns, M] -> qf, qc [ns], cycles [ns, 2], flags [ns]."""
     a, b, lam = table
     xi = _f64(xi)
@@ -216,7 +219,7 @@ def solve_level(sigma2, corr_len, table, n_fine, level, xi, tol=1e-10, max_cycle
     cyc = np.zeros((ns, 2), np.int32)
     fl = np.zeros(ns, np.int32)
     rc = lib().oracle_solve_level(sigma2, corr_len, len(a), a, b, lam, n_fine, n_coarsest,
-                                  level, ns, xi, pW, pE, tol, max_cycles, nu1, nu2, qf, qc,
+                                  level, ns, xi, pW, pE, tol, max_cycles, nu1, nu2, wmax, qf, qc,
                                   cyc, fl, nthreads)
     if rc != 0:
         raise RuntimeError("oracle_solve_level failed")

@@ -9,29 +9,45 @@ CFG1 = dict(sigma2=1.0, corr_len=0.3, M=64)
 
 
 def test_vcycle_factor_below_0p2_cfg1():
-    """Residual reduction per V(2,2) cycle on the 3-level config (16^2, 32^2, 64^2).
-
-    For each QoI stage the mean reduction per cycle (geometric mean from the
-    first to the last cycle down to tol 1e-10) is below 0.2 for 90% of the
-    samples and about 0.1 at the median; a few percent of the rough samples
-    converge at up to ~0.26 per cycle.
-    """
+    """Residual reduction factor below 0.2 on every cycle of every QoI stage,
+    on the 3-level config (16^2, 32^2, 64^2), down to the round-off floor."""
     tab = O.kl_table(CFG1["sigma2"], CFG1["corr_len"], CFG1["M"])
-    factors = []
+    worst = 0.0
     for lev, n in enumerate([16, 32, 64]):
         xi = inputs.mc_normals(60, 64, config=1, level=lev)
         for s in range(xi.shape[0]):
             K = O.field(n, CFG1["corr_len"], tab, xi[s])
-            out = O.fmg_sample(K, level=lev, tol=1e-10, max_cycles=60, history=True)
+            out = O.fmg_sample(K, level=lev, tol=1e-13, max_cycles=60, history=True)
             assert out["flags"] == 0
             for h in out["hist"]:
-                h = h[h > 0]
-                if len(h) > 2:
-                    factors.append((h[-1] / h[0]) ** (1.0 / (len(h) - 1)))
-    factors = np.array(factors)
-    assert np.median(factors) < 0.12
-    assert np.percentile(factors, 90) < 0.2
-    assert factors.max() < 0.3
+                h = h[h > 1e-13]
+                if len(h) > 1:
+                    worst = max(worst, float(np.max(h[1:] / h[:-1])))
+    assert 0.0 < worst < 0.2, worst
+
+
+def test_pure_v_cycle_is_slower_but_converges_to_the_same_q():
+    """The W-cycle coarse corrections change the cost, not the converged QoI."""
+    tab = O.kl_table(1.0, 0.2, 256)
+    xi = inputs.mc_normals(4, 256, config=2, level=2, purpose=1)
+    w = O.solve_level(1.0, 0.2, tab, 128, 2, xi, tol=1e-14, max_cycles=100)
+    v = O.solve_level(1.0, 0.2, tab, 128, 2, xi, tol=1e-14, max_cycles=100, wmax=0)
+    assert np.all(v[2][:, 1] >= w[2][:, 1])
+    assert np.max(np.abs(w[0] - v[0]) / np.abs(w[0])) < 1e-11
+    assert np.max(np.abs(w[1] - v[1]) / np.abs(w[1])) < 1e-11
+
+
+def test_hard_sample_converges():
+    """A 512^2 sample (index 2192 of the 4096-sample set, log k spanning about
+    -3.3..4.05) on which V(2,2) cycles with these coarse operators diverge;
+    with W-cycle corrections below 128^2 it converges in a few cycles."""
+    tab = O.kl_table(1.0, 0.2, 256)
+    xi = inputs.mc_normals(4096, 256, config=2, level=4)[2192]
+    K = O.field(256, 0.2, tab, xi)
+    out = O.fmg_sample(K, level=1, tol=1e-10, max_cycles=30)
+    assert out["flags"] == 0 and out["cycles"][1] <= 8
+    bad = O.fmg_sample(K, level=1, tol=1e-10, max_cycles=30, wmax=0)
+    assert bad["flags"] & 1
 
 
 def test_coarse_qoi_is_level_below_fine_qoi():
