@@ -85,7 +85,8 @@ typedef struct {
     int32_t max_cycles;    /* cap on V-cycles per QoI stage (>= 1) */
     int32_t inner_cycles;  /* FP32 V-cycles per FP64 refinement step (FP32_IR), >= 1 */
     int32_t max_batch;     /* samples resident on the device at once (0 = library default) */
-    int32_t reserved;      /* 0 */
+    int32_t w_max_n;       /* coarse-grid corrections on grids with n <= w_max_n (other than the
+                              coarsest) are two cycles in succession (W-cycle); 0 = V-cycles only */
     double rel_tol;        /* stop when ||b - A p||_2 <= rel_tol ||b||_2 at a QoI stage */
 } fmgmc_opts;
 

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -237,16 +238,19 @@ struct Bufs {
 Bufs<double> bufs64(fmgmc_ctx *c) { return {c->K64, c->x64, c->b64, c->pf64}; }
 Bufs<float> bufs32(fmgmc_ctx *c) { return {c->K32, c->x32, c->b32, c->pf32}; }
 
-// One V(nu1,nu2) cycle with top grid k: top operator from K (stage operator),
-// the levels below from correction pyramid q. rhs_array: top rhs in b[k]
-// (else the Dirichlet data). init: INIT_ZERO / INIT_LOAD / INIT_INTERP (from x[k-1]).
+// One cycle with top grid k: top operator from K (stage operator), the levels
+// below from correction pyramid q; V(nu1,nu2) on grids above w_max_n, two
+// coarse cycles (W) on grids n <= w_max_n. rhs_array: top rhs in b[k] (else the
+// Dirichlet data). init: INIT_ZERO / INIT_LOAD / INIT_INTERP (from x[k-1]).
 template <typename T>
 int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_array, int out_top,
            hipStream_t st) {
     const int nh1 = 2 * c->opts.nu1, nh2 = 2 * c->opts.nu2;
-    const int Ls = std::min(k, c->small_top);
     const int N0 = c->nsz[0] * c->nsz[0];
     const double pW = c->hier.p_west, pE = c->hier.p_east;
+    const double *chol_pyr = c->chol + size_t(1 + q) * S * N0 * N0;
+    const double *chol_stage = c->chol;
+    auto gamma = [&](int j) { return (j > 0 && c->nsz[j] <= c->opts.w_max_n) ? 2 : 1; };
     auto small = [&](int top, bool from_k, int sinit, bool srhs, int sout, const double *chol) {
         SmallArgs<T> a{};
         a.top = top;
@@ -265,10 +269,9 @@ int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_arra
         a.pE = pE;
         a.nu1 = c->opts.nu1;
         a.nu2 = c->opts.nu2;
+        a.wmax = c->opts.w_max_n;
         return launch_small(a, S, sinit, srhs, sout, st);
     };
-    const double *chol_pyr = c->chol + size_t(1 + q) * S * N0 * N0;
-    const double *chol_stage = c->chol;
     if (k <= c->small_top) {
         // whole cycle in LDS (k == 0: the direct solve with the stage operator)
         return small(k, true, init, rhs_array, out_top, k == 0 ? chol_stage : chol_pyr);
@@ -289,6 +292,13 @@ int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_arra
         a.pE = pE;
         return launch_march(a, S, nh, ck, minit, rhsa, mout, st);
     };
+    // cycle rooted at correction level j (rhs b[j], faces of pyramid q)
+    std::function<int(int, int)> corr = [&](int j, int cinit) -> int {
+        if (j <= c->small_top) return small(j, false, cinit, true, 0, chol_pyr);
+        TRY(march(j, false, cinit, true, OUT_RESTRICT, nh1));
+        for (int g = 0; g < gamma(j - 1); ++g) TRY(corr(j - 1, g == 0 ? INIT_ZERO : INIT_LOAD));
+        return march(j, false, INIT_PROLONG, true, 0, nh2);
+    };
     // algorithmic bytes per cell of the top-grid passes (each operand once)
     const double w = sizeof(T), cells = double(c->nsz[k]) * c->nsz[k];
     const bool top = (k == c->top_grid);
@@ -298,10 +308,7 @@ int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_arra
     const double b_post = w + 0.25 * w + w + (rhs_array ? w : 0.0) + w;
     if (top) TRY(timed(c, FMGMC_PROF_PRE, act * cells * b_pre, st, [&] { return march(k, true, init, rhs_array, OUT_RESTRICT, nh1); }));
     else TRY(march(k, true, init, rhs_array, OUT_RESTRICT, nh1));
-    for (int j = k - 1; j > Ls; --j) TRY(march(j, false, INIT_ZERO, true, OUT_RESTRICT, nh1));
-    if (top) TRY(timed(c, FMGMC_PROF_SMALL, 0.0, st, [&] { return small(Ls, false, INIT_ZERO, true, 0, chol_pyr); }));
-    else TRY(small(Ls, false, INIT_ZERO, true, 0, chol_pyr));
-    for (int j = Ls + 1; j < k; ++j) TRY(march(j, false, INIT_PROLONG, true, 0, nh2));
+    for (int g = 0; g < gamma(k - 1); ++g) TRY(corr(k - 1, g == 0 ? INIT_ZERO : INIT_LOAD));
     if (top) TRY(timed(c, FMGMC_PROF_POST, act * cells * b_post, st, [&] { return march(k, true, INIT_PROLONG, rhs_array, out_top, nh2); }));
     else TRY(march(k, true, INIT_PROLONG, rhs_array, out_top, nh2));
     return FMGMC_OK;
@@ -451,7 +458,7 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
     if (o->nu1 < 1 || o->nu1 > 2 || o->nu2 < 1 || o->nu2 > 2 || o->max_cycles < 1 || !(o->rel_tol > 0))
         return FMGMC_EINVAL;
     if (o->solver == FMGMC_SOLVER_FP32_IR && h->n0 < 8) return FMGMC_EINVAL;  // QoI stages need n >= 8
-    if (o->max_batch < 0) return FMGMC_EINVAL;
+    if (o->max_batch < 0 || o->w_max_n < 0) return FMGMC_EINVAL;
     return FMGMC_OK;
 }
 

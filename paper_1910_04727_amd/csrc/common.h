@@ -90,6 +90,7 @@ struct SmallArgs {
     const int32_t *active;
     double pW, pE;
     int nu1, nu2;
+    int wmax;             // coarse grids with n <= wmax (not the coarsest) are cycled twice
 };
 template <typename T>
 int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out, hipStream_t st);

@@ -2,44 +2,62 @@
 // finite-volume operator (Section 3.1 (1)), used by the V-cycles of the full
 // multigrid pass (Section 2.5).
 //
-// Design (gfx950): one workgroup owns one sample and one lane owns one grid
-// column (n <= 1024 lanes). The workgroup marches up the rows. At step F it
-// loads row F once from HBM, then applies half-sweep t (t = 1..NH, red first)
-// to row F - t. This is the wavefront order of the sweeps, so the result is
-// exactly that of NH sequential half-sweeps. The residual follows at row
-// F - NH - 1, is summed over 2x2 blocks into the next coarser grid, and/or
-// squared into the sample's residual norm.
-// Every cell is read and written once per pass: x, K (or the face arrays) and b
-// stream through HBM, whatever NH is. Rows in flight live in an LDS ring
-// (neighbours in other lanes); per-row coefficients live in a register ring.
-// One barrier per row step: every cross-lane read in step F is of data written
-// before step F's barrier.
+// Design (gfx950): one workgroup owns one sample; lane l owns the two cells
+// of columns 2l and 2l+1 of every row, one red and one black, so every lane
+// updates exactly one cell in every half-sweep. The workgroup marches up the
+// rows. At step F it takes row F (loaded NH+1 steps earlier into a register
+// queue, so HBM latency overlaps the work of NH+1 rows) and applies half-sweep
+// t (t = 1..NH, red first) to row F - t: this is the wavefront order of the
+// sweeps, so the result is exactly that of NH sequential half-sweeps. The
+// residual follows at row F - NH - 1 and is summed over 2x2 blocks into the
+// next coarser grid and/or squared into the sample's residual norm. Every
+// cell is read and written once per pass.
+// Rows in flight live in an LDS ring padded with a zero column on each side
+// (so boundary neighbours contribute nothing without a branch); per-row
+// coefficients live in a register ring. One barrier per row step: every
+// cross-lane read in step F is of data written before step F's barrier.
 #include "common.h"
 
 namespace fmgmc {
 
 template <typename T>
+struct V2 {
+    T a, b;
+};
+
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) {
+    // hardware reciprocal refined by two Newton steps (full double precision)
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+template <typename T>
 __device__ __forceinline__ T harm(T a, T b) {
-    return T(2) * a * b / (a + b);
+    return T(2) * a * b * rcp_(a + b);
 }
 
-// coarse value with ghost cells: mirror across north/south, 2 g - v across west/east
 template <typename T>
-__device__ __forceinline__ T coarse_at(const T *__restrict__ c, int nc, int I, int J, T gW, T gE) {
-    J = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
-    if (I < 0) return T(2) * gW - c[J * nc];
-    if (I >= nc) return T(2) * gE - c[J * nc + nc - 1];
-    return c[J * nc + I];
+__device__ __forceinline__ V2<T> ld2(const T *p) {
+    if constexpr (sizeof(T) == 8) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        return {T(v.x), T(v.y)};
+    } else {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        return {T(v.x), T(v.y)};
+    }
 }
 
-// bilinear cell-centred interpolation, weights 9, 3, 3, 1 over 16
 template <typename T>
-__device__ __forceinline__ T bilinear(const T *__restrict__ c, int nc, int i, int j, T gW, T gE) {
-    const int I = i >> 1, J = j >> 1;
-    const int di = (i & 1) ? 1 : -1, dj = (j & 1) ? 1 : -1;
-    return (T(9) * coarse_at(c, nc, I, J, gW, gE) + T(3) * coarse_at(c, nc, I + di, J, gW, gE) +
-            T(3) * coarse_at(c, nc, I, J + dj, gW, gE) + coarse_at(c, nc, I + di, J + dj, gW, gE)) /
-           T(16);
+__device__ __forceinline__ void st2(T *p, T a, T b) {
+    if constexpr (sizeof(T) == 8) {
+        *reinterpret_cast<double2 *>(p) = double2{a, b};
+    } else {
+        *reinterpret_cast<float2 *>(p) = float2{a, b};
+    }
 }
 
 template <typename T>
@@ -58,43 +76,65 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
 }
 
 template <typename T, int NH, bool CK, int INIT, bool RHSA, int OUT>
-__global__ __launch_bounds__(1024) void k_march(MarchArgs<T> A) {
-    constexpr int R = NH + 3;  // x rows alive in LDS: F - NH - 2 .. F
-    constexpr int U = NH + 1;  // coefficient rows alive in registers: F - NH - 1 .. F - 1
+__global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
+    constexpr int U = NH + 1;    // register ring depth = prefetch distance = unroll
+    constexpr int RX = 8;        // LDS x ring rows (>= NH + 3), power of two
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
-    const int n = A.n;
-    const int i = threadIdx.x;
+    constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
+    constexpr bool LX = (INIT == INIT_LOAD || INIT == INIT_PROLONG);
+    const int n = A.n, nl = n >> 1, nc = n >> 1;
+    const int l = threadIdx.x;
     const int s = blockIdx.x;
     if (A.active && A.active[s] == 0) return;  // uniform over the block
 
     extern __shared__ unsigned char smem_raw[];
-    T *xs = reinterpret_cast<T *>(smem_raw);  // [R][n] x rows
-    T *ks = xs + R * n;                       // [3][n] K rows (CK) or west faces
-    T *red = ks + 3 * n;                      // [16] reduction scratch
+    const int XS = n + 4;                               // x row: [pad, pad, cells 0..n-1, pad, pad]
+    T *xs = reinterpret_cast<T *>(smem_raw);            // [RX][XS]
+    T *ks = xs + RX * XS;                               // [4][n] K (stage) or west faces (correction)
+    T *cs = ks + 4 * n;                                 // [4][nc] coarse rows (prolongation source)
+    T *red = cs + 4 * nc;                               // [16]
+    for (int k = l; k < RX * XS; k += blockDim.x) xs[k] = T(0);
+    __syncthreads();
 
     const size_t base = size_t(s) * n * n;
-    const int nc = n >> 1;
     const size_t cbase = size_t(s) * nc * nc;
     const T gW = T(A.pW), gE = T(A.pE);
+    const T cgW = (INIT == INIT_INTERP) ? gW : T(0), cgE = (INIT == INIT_INTERP) ? gE : T(0);
+    const bool first = (l == 0), last = (l == nl - 1);
 
-    // register ring of per-row coefficients, slot = row % U (static after unrolling)
-    T tw[U], te[U], tn[U], ts[U], id[U], bv[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) { tw[k] = te[k] = tn[k] = ts[k] = id[k] = bv[k] = T(0); }
-    T fy_prev = T(0), fy_cur = T(0);  // south faces of rows F-1, F (face mode)
-    T b_old = T(0), b_new = T(0);     // rhs of rows F-1, F (array mode)
-    T rprev = T(0);                   // residual of the previous (even) row
-    T rr = T(0), q = T(0);
-
-    // rhs of a row: given, or the Dirichlet data entering through the side faces
-    auto rhs = [&](int slot) -> T {
-        if (RHSA) return bv[slot];
-        T b0 = T(0);
-        if (i == 0) b0 += tw[slot] * gW;
-        if (i == n - 1) b0 += te[slot] * gE;
-        return b0;
+    // prefetch queue, slot = row % U
+    V2<T> qx[U], qk[U], qb[U], qf[U];
+    T qc[U], qe[U];
+    auto fetch = [&](int slot, int row) {
+        const size_t idx = base + size_t(row) * n + 2 * l;
+        if (LX) qx[slot] = ld2(A.x + idx);
+        if (CK) {
+            qk[slot] = ld2(A.K + idx);
+        } else {
+            qk[slot] = ld2(A.f.fx + idx);
+            qf[slot] = ld2(A.f.fy + idx);
+            qe[slot] = A.f.fxe[size_t(s) * n + row];
+        }
+        if (RHSA) qb[slot] = ld2(A.b + idx);
+        if (CO) {
+            const int J = min((row + 1) >> 1, nc - 1);
+            qc[slot] = A.xc[cbase + size_t(J) * nc + l];
+        }
     };
-    auto xrow = [&](int row) -> T * { return xs + (row % R) * n; };
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (u < n) fetch(u, u);
+
+    // coefficient ring, slot = row % U: faces west of cell 0, between the cells,
+    // east of cell 1; south / north faces and 1/diagonal of both cells; rhs.
+    T rw[U], rm[U], re[U], rs0[U], rs1[U], rn0[U], rn1[U], ri0[U], ri1[U], rb0[U], rb1[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+        rw[k] = rm[k] = re[k] = rs0[k] = rs1[k] = rn0[k] = rn1[k] = ri0[k] = ri1[k] = rb0[k] = rb1[k] = T(0);
+    V2<T> kprev{T(0), T(0)}, kcur{T(0), T(0)};   // own K (or south faces) of rows F-1, F
+    V2<T> bprev{T(0), T(0)}, bcur{T(0), T(0)};
+    T eprev = T(0), ecur = T(0);                 // east boundary face of rows F-1, F (correction)
+    T rprev = T(0), rr = T(0), q = T(0);
 
     const int LAST = n - 1 + NH + (RES ? 1 : 0);
     for (int F0 = 0; F0 <= LAST; F0 += U) {
@@ -102,107 +142,134 @@ __global__ __launch_bounds__(1024) void k_march(MarchArgs<T> A) {
         for (int u = 0; u < U; ++u) {
             const int F = F0 + u;
             if (F > LAST) break;
-            // ---- 1. load row F
+            T *xrow = xs + (F & (RX - 1)) * XS + 2;
+            // ---- 1. take row F from the queue into LDS, refill the slot with row F + U
+            kprev = kcur;
+            bprev = bcur;
+            eprev = ecur;
+            V2<T> xraw{T(0), T(0)};
             if (F < n) {
-                const size_t idx = base + size_t(F) * n + i;
-                T xv;
-                if (INIT == INIT_ZERO) xv = T(0);
-                else if (INIT == INIT_LOAD) xv = A.x[idx];
-                else if (INIT == INIT_PROLONG) xv = A.x[idx] + bilinear(A.xc + cbase, nc, i, F, T(0), T(0));
-                else xv = bilinear(A.xc + cbase, nc, i, F, gW, gE);
-                xrow(F)[i] = xv;
-                if (CK) {
-                    ks[(F % 3) * n + i] = A.K[idx];
-                } else {
-                    ks[(F % 3) * n + i] = A.f.fx[idx];
-                    fy_prev = fy_cur;
-                    fy_cur = A.f.fy[idx];
-                }
-                if (RHSA) {
-                    b_old = b_new;
-                    b_new = A.b[idx];
-                }
+                if (LX) xraw = qx[u];
+                if (LX) st2(xrow + 2 * l, xraw.a, xraw.b);
+                else if (INIT == INIT_ZERO) st2(xrow + 2 * l, T(0), T(0));
+                st2(ks + (F & 3) * n + 2 * l, qk[u].a, qk[u].b);
+                kcur = CK ? qk[u] : qf[u];
+                if (RHSA) bcur = qb[u];
+                if (!CK) ecur = qe[u];
+                if (CO) cs[(((F + 1) >> 1) & 3) * nc + l] = qc[u];
+                if (F + U < n) fetch(u, F + U);
             } else {
-                fy_prev = fy_cur;
-                fy_cur = T(0);
-                b_old = b_new;
+                kcur = {T(0), T(0)};
             }
             __syncthreads();
-            // ---- 2. coefficients of row r = F - 1
+            // ---- 2. coarse-grid correction / FMG interpolation of row F (own cells)
+            if (CO && F < n) {
+                const int J0 = F >> 1, J1 = min(max(J0 + ((F & 1) ? 1 : -1), 0), nc - 1);
+                const T *c0 = cs + (J0 & 3) * nc, *c1 = cs + (J1 & 3) * nc;
+                const T a0 = c0[l], a1 = c1[l];
+                const T w0 = first ? T(2) * cgW - a0 : c0[max(l - 1, 0)];
+                const T w1 = first ? T(2) * cgW - a1 : c1[max(l - 1, 0)];
+                const T e0 = last ? T(2) * cgE - a0 : c0[min(l + 1, nc - 1)];
+                const T e1 = last ? T(2) * cgE - a1 : c1[min(l + 1, nc - 1)];
+                const T p0 = (T(9) * a0 + T(3) * w0 + T(3) * a1 + w1) / T(16);
+                const T p1 = (T(9) * a0 + T(3) * e0 + T(3) * a1 + e1) / T(16);
+                if (INIT == INIT_PROLONG) st2(xrow + 2 * l, xraw.a + p0, xraw.b + p1);
+                else st2(xrow + 2 * l, p0, p1);
+            }
+            // ---- 3. coefficients of row r = F - 1
             {
                 const int r = F - 1;
                 const int sr = (u + U - 1) % U, sp = (u + U - 2) % U;
                 if (r >= 0 && r < n) {
-                    const T *kr = ks + (r % 3) * n;
-                    T w_, e_, n_, s_;
+                    const T *kr = ks + (r & 3) * n;
+                    T w_, m_, e_, s0, s1, n0, n1;
                     if (CK) {
-                        const T k0 = kr[i];
-                        w_ = (i > 0) ? harm(kr[i - 1], k0) : T(2) * k0;
-                        e_ = (i < n - 1) ? harm(k0, kr[i + 1]) : T(2) * k0;
-                        n_ = (r + 1 < n) ? harm(k0, ks[((r + 1) % 3) * n + i]) : T(0);
-                        s_ = (r > 0) ? tn[sp] : T(0);
+                        const T k0 = kprev.a, k1 = kprev.b;
+                        w_ = first ? T(2) * k0 : harm(kr[max(2 * l - 1, 0)], k0);
+                        m_ = harm(k0, k1);
+                        e_ = last ? T(2) * k1 : harm(k1, kr[min(2 * l + 2, n - 1)]);
+                        n0 = (r + 1 < n) ? harm(k0, kcur.a) : T(0);
+                        n1 = (r + 1 < n) ? harm(k1, kcur.b) : T(0);
+                        s0 = (r > 0) ? rn0[sp] : T(0);
+                        s1 = (r > 0) ? rn1[sp] : T(0);
                     } else {
-                        w_ = kr[i];
-                        e_ = (i < n - 1) ? kr[i + 1] : A.f.fxe[size_t(s) * n + r];
-                        s_ = fy_prev;
-                        n_ = (r + 1 < n) ? fy_cur : T(0);
+                        w_ = kr[2 * l];
+                        m_ = kr[2 * l + 1];
+                        e_ = last ? eprev : kr[min(2 * l + 2, n - 1)];
+                        s0 = kprev.a;
+                        s1 = kprev.b;
+                        n0 = kcur.a;
+                        n1 = kcur.b;
                     }
-                    tw[sr] = w_;
-                    te[sr] = e_;
-                    tn[sr] = n_;
-                    ts[sr] = s_;
-                    id[sr] = T(1) / (((w_ + e_) + s_) + n_);
-                    if (RHSA) bv[sr] = b_old;
+                    rw[sr] = w_;
+                    rm[sr] = m_;
+                    re[sr] = e_;
+                    rs0[sr] = s0;
+                    rs1[sr] = s1;
+                    rn0[sr] = n0;
+                    rn1[sr] = n1;
+                    ri0[sr] = rcp_(((w_ + m_) + s0) + n0);
+                    ri1[sr] = rcp_(((m_ + e_) + s1) + n1);
+                    if (RHSA) {
+                        rb0[sr] = bprev.a;
+                        rb1[sr] = bprev.b;
+                    } else {
+                        rb0[sr] = first ? w_ * gW : T(0);
+                        rb1[sr] = last ? e_ * gE : T(0);
+                    }
                 }
             }
-            // ---- 3. half-sweeps: sweep t on row F - t (colour (t-1) & 1)
+            // ---- 4. half-sweeps: sweep t on row F - t, colour (t-1) & 1
 #pragma unroll
             for (int t = 1; t <= NH; ++t) {
                 const int r = F - t;
-                if (r >= 0 && r < n && ((i + r) & 1) == ((t - 1) & 1)) {
+                if (r >= 0 && r < n) {
                     const int sr = (u + 2 * U - t) % U;
-                    T *row = xrow(r);
-                    T acc = rhs(sr);
-                    if (i > 0) acc += tw[sr] * row[i - 1];
-                    if (i < n - 1) acc += te[sr] * row[i + 1];
-                    if (r > 0) acc += ts[sr] * xrow(r + R - 1)[i];
-                    if (r + 1 < n) acc += tn[sr] * xrow(r + 1)[i];
-                    row[i] = acc * id[sr];
+                    T *row = xs + (r & (RX - 1)) * XS + 2;
+                    const T *up = xs + ((r + 1) & (RX - 1)) * XS + 2;
+                    const T *dn = xs + ((r - 1) & (RX - 1)) * XS + 2;
+                    if (((t - 1 + r) & 1) == 0) {  // this lane's red/black cell is column 2l
+                        const T v = (((rb0[sr] + rw[sr] * row[2 * l - 1]) + rm[sr] * row[2 * l + 1]) +
+                                     rs0[sr] * dn[2 * l] + rn0[sr] * up[2 * l]) * ri0[sr];
+                        row[2 * l] = v;
+                    } else {                        // column 2l + 1
+                        const T v = (((rb1[sr] + rm[sr] * row[2 * l]) + re[sr] * row[2 * l + 2]) +
+                                     rs1[sr] * dn[2 * l + 1] + rn1[sr] * up[2 * l + 1]) * ri1[sr];
+                        row[2 * l + 1] = v;
+                    }
                 }
             }
-            // ---- 4. residual of row r = F - NH - 1
+            // ---- 5. residual of row r = F - NH - 1
             if (RES) {
                 const int r = F - NH - 1;
                 if (r >= 0 && r < n) {
                     const int sr = (u + 2 * U - NH - 1) % U;
-                    const T *row = xrow(r);
-                    const T xv = row[i];
-                    T acc = rhs(sr);
-                    if (i > 0) acc += tw[sr] * row[i - 1];
-                    if (i < n - 1) acc += te[sr] * row[i + 1];
-                    if (r > 0) acc += ts[sr] * xrow(r + R - 1)[i];
-                    if (r + 1 < n) acc += tn[sr] * xrow(r + 1)[i];
-                    const T res = acc - (((tw[sr] + te[sr]) + ts[sr]) + tn[sr]) * xv;
-                    if (OUT & OUT_RR) rr += res * res;
+                    const T *row = xs + (r & (RX - 1)) * XS + 2;
+                    const T *up = xs + ((r + 1) & (RX - 1)) * XS + 2;
+                    const T *dn = xs + ((r - 1) & (RX - 1)) * XS + 2;
+                    const T x0 = row[2 * l], x1 = row[2 * l + 1];
+                    const T d0 = ((rw[sr] + rm[sr]) + rs0[sr]) + rn0[sr];
+                    const T d1 = ((rm[sr] + re[sr]) + rs1[sr]) + rn1[sr];
+                    const T res0 = (((rb0[sr] + rw[sr] * row[2 * l - 1]) + rm[sr] * x1) + rs0[sr] * dn[2 * l] +
+                                    rn0[sr] * up[2 * l]) - d0 * x0;
+                    const T res1 = (((rb1[sr] + rm[sr] * x0) + re[sr] * row[2 * l + 2]) + rs1[sr] * dn[2 * l + 1] +
+                                    rn1[sr] * up[2 * l + 1]) - d1 * x1;
+                    if (OUT & OUT_RR) rr += res0 * res0 + res1 * res1;
                     if (OUT & OUT_RESTRICT) {
-                        if (r & 1) {
-                            T v = res + rprev;
-                            v += __shfl_xor(v, 1);
-                            if ((i & 1) == 0) A.bc[cbase + size_t(r >> 1) * nc + (i >> 1)] = v;
-                        } else {
-                            rprev = res;
-                        }
+                        if (r & 1) A.bc[cbase + size_t(r >> 1) * nc + l] = ((rprev + res0) + res1);
+                        else rprev = res0 + res1;
                     }
                 }
             }
-            // ---- 5. write back the finished row F - NH
+            // ---- 6. write back the finished row F - NH
             {
                 const int r = F - NH;
                 if (r >= 0 && r < n) {
                     const int sr = (u + 2 * U - NH) % U;
-                    const T xv = xrow(r)[i];
-                    A.x[base + size_t(r) * n + i] = xv;
-                    if ((OUT & OUT_Q) && i == n - 1) q += te[sr] * (xv - gE);
+                    const T *row = xs + (r & (RX - 1)) * XS + 2;
+                    const T x0 = row[2 * l], x1 = row[2 * l + 1];
+                    st2(A.x + base + size_t(r) * n + 2 * l, x0, x1);
+                    if ((OUT & OUT_Q) && last) q += re[sr] * (x1 - gE);
                 }
             }
         }
@@ -211,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_march(MarchArgs<T> A) {
         const T t = block_sum(rr, red);
         if (threadIdx.x == 0) A.rr[s] = double(t);
     }
-    if ((OUT & OUT_Q) && i == n - 1) A.q[s] = double(q);
+    if ((OUT & OUT_Q) && last) A.q[s] = double(q);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -219,8 +286,8 @@ template <typename T, int NH>
 static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool rhsa, int out,
                           hipStream_t st) {
     const int n = a.n;
-    const size_t lds = (size_t(NH + 3) * n + 3 * n + 16) * sizeof(T);
-    dim3 grid(S), block(n);
+    const size_t lds = (size_t(8) * (n + 4) + 4 * size_t(n) + 4 * size_t(n / 2) + 16) * sizeof(T);
+    dim3 grid(S), block(n / 2);
 #define FMGMC_MARCH_CASE(CKV, INITV, RHSV, OUTV)                                               \
     if (ck == CKV && init == INITV && rhsa == RHSV && out == (OUTV)) {                         \
         hipLaunchKernelGGL((k_march<T, NH, CKV, INITV, RHSV, OUTV>), grid, block, lds, st, a);  \
@@ -236,6 +303,7 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
     FMGMC_MARCH_CASE(true, INIT_PROLONG, true, 0)
     // correction operators (levels below the top)
     FMGMC_MARCH_CASE(false, INIT_ZERO, true, OUT_RESTRICT)
+    FMGMC_MARCH_CASE(false, INIT_LOAD, true, OUT_RESTRICT)
     FMGMC_MARCH_CASE(false, INIT_PROLONG, true, 0)
 #undef FMGMC_MARCH_CASE
     set_error("launch_march: unsupported variant");
@@ -245,8 +313,8 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
 template <typename T>
 int launch_march(const MarchArgs<T> &a, int S, int nhalf, bool coef_from_k, int init, bool rhs_array,
                  int out, hipStream_t st) {
-    if (a.n < 8 || a.n > 1024 || (a.n & (a.n - 1))) {
-        set_error("launch_march: n must be a power of two in [8, 1024]");
+    if (a.n < 16 || a.n > 1024 || (a.n & (a.n - 1))) {
+        set_error("launch_march: n must be a power of two in [16, 1024]");
         return FMGMC_EINVAL;
     }
     if (S <= 0) return FMGMC_OK;

@@ -1,5 +1,6 @@
 // Small grids (n <= 32): one workgroup holds a sample's whole sub-hierarchy
-// in LDS and runs a complete V(nu1,nu2) cycle: red-black Gauss-Seidel,
+// in LDS and runs a complete cycle (V(nu1,nu2), with W-cycle coarse-grid
+// corrections on grids n <= wmax): red-black Gauss-Seidel,
 // residual restriction by 2x2 sums, bilinear prolongation, and the direct
 // solve on the coarsest grid (Section 2.5; Cholesky factor precomputed in
 // FP64). With top == 0 the call is the coarsest-grid direct solve itself
@@ -171,31 +172,52 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     }
     __syncthreads();
 
-    // V-cycle: descend
-    for (int k = top; k >= 1; --k) {
-        smooth(L[k], A.nu1);
-        const int n = L[k].n, nc = n / 2;
-        for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
-            const int I = c % nc, J = c / nc;
-            T acc = T(0);
-            for (int dj = 0; dj < 2; ++dj)
-                for (int di = 0; di < 2; ++di) {
-                    const int i = 2 * I + di, j = 2 * J + dj;
-                    acc += nbsum(L[k], i, j) - diag(L[k], i, j) * L[k].x[j * n + i];
-                }
-            L[k - 1].b[c] = acc;
-            L[k - 1].x[c] = T(0);
+    // Cycle on levels top..0, iterative: descending from level k runs the
+    // pre-smoothing and restriction, then cnt[k] coarse cycles (two when the
+    // coarse grid is not the coarsest and has n <= wmax, a W-cycle; else one),
+    // then prolongation and post-smoothing. Control flow is uniform.
+    int cnt[kMaxLev];
+    int k = top;
+    bool down = true;
+    while (true) {
+        if (down) {
+            if (k == 0) {
+                chol_solve16(Ls, N0, L[0].b, L[0].x, y);
+                if (top == 0) break;
+                k = 1;
+                down = false;
+                continue;
+            }
+            smooth(L[k], A.nu1);
+            const int n = L[k].n, nc = n / 2;
+            for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
+                const int I = c % nc, J = c / nc;
+                T acc = T(0);
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di) {
+                        const int i = 2 * I + di, j = 2 * J + dj;
+                        acc += nbsum(L[k], i, j) - diag(L[k], i, j) * L[k].x[j * n + i];
+                    }
+                L[k - 1].b[c] = acc;
+                L[k - 1].x[c] = T(0);
+            }
+            __syncthreads();
+            cnt[k] = (k - 1 > 0 && L[k - 1].n <= A.wmax) ? 2 : 1;
+            k = k - 1;
+        } else {
+            if (--cnt[k] > 0) {  // run the coarse cycle again from its current iterate
+                k = k - 1;
+                down = true;
+                continue;
+            }
+            const int n = L[k].n, nc = n / 2;
+            for (int c = threadIdx.x; c < n * n; c += blockDim.x)
+                L[k].x[c] += interp_at(L[k - 1].x, nc, c % n, c / n, T(0), T(0));
+            __syncthreads();
+            smooth(L[k], A.nu2);
+            if (k == top) break;
+            k = k + 1;
         }
-        __syncthreads();
-    }
-    chol_solve16(Ls, N0, L[0].b, L[0].x, y);
-    // ascend
-    for (int k = 1; k <= top; ++k) {
-        const int n = L[k].n, nc = n / 2;
-        for (int c = threadIdx.x; c < n * n; c += blockDim.x)
-            L[k].x[c] += interp_at(L[k - 1].x, nc, c % n, c / n, T(0), T(0));
-        __syncthreads();
-        smooth(L[k], A.nu2);
     }
 
     // outputs

@@ -285,3 +285,35 @@ def test_512_batch_sampled_against_oracle(solver, tol, bound):
         assert np.max(np.abs(qc[pick] - oqc) / np.abs(oqc)) <= bound
     # properties that hold for every sample of the batch
     assert np.all(np.isfinite(qf)) and np.all(qf > 0) and np.all(cyc[:, 1] >= 1)
+
+
+# ------------------------------------------------------------- cycle variants
+def test_pure_v_cycles_match_oracle():
+    """w_max_n = 0: plain V(2,2) cycles on both sides."""
+    cfg = CFG2
+    level, S = 2, 6
+    n = cfg["n0"] << level
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=3)
+    log(f"fp64 pure V n {n} S {S}")
+    with fmgmc.Context(**cfg, w_max_n=0) as ctx:
+        rc, qf, qc, cyc, fl = run_level(ctx, level, xi)
+    oqf, oqc, ocyc, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), n, level, xi, wmax=0)
+    assert_same_solution(qf, oqf, cyc[:, 1:], ocyc[:, 1:], 1e-10, "  qf")
+    assert_same_solution(qc, oqc, cyc[:, :1], ocyc[:, :1], 1e-10, "  qc")
+
+
+@pytest.mark.parametrize("solver", ["fp64", "fp32_ir"])
+def test_hard_high_contrast_sample(solver):
+    """Sample 2192 of the 512^2 set (log k from -3.3 to 4.05): pure V-cycles
+    diverge on it; the W-cycle coarse corrections converge in a few cycles."""
+    cfg = CFG2
+    xi = inputs.mc_normals(4096, cfg["n_modes"], config=2, level=4)[2190:2194]
+    log(f"hard sample {solver}")
+    with fmgmc.Context(**cfg, solver=solver) as ctx:
+        rc, qf, qc, cyc, fl = run_level(ctx, 4, xi)
+    assert rc == fmgmc.OK and np.all(fl == 0) and cyc.max() <= 10, cyc
+    oqf, oqc, ocyc, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), 512, 4, xi, nthreads=4)
+    if solver == "fp64":
+        assert_same_solution(qf, oqf, cyc[:, 1:], ocyc[:, 1:], 1e-10, "  qf")
+    else:
+        assert np.max(np.abs(qf - oqf) / np.abs(oqf)) < 1e-6
