@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--forms", default="fp32_ir,fp64")
     ap.add_argument("--cpu-samples", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (the method's samples are independent; "
@@ -126,6 +128,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
     xi = inputs.mc_normals(args.samples, CFG["n_modes"], config=2, level=LEVEL)
     xi_dev = torch.from_numpy(xi).to("cuda")
     torch.cuda.synchronize()

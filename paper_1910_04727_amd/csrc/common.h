@@ -81,7 +81,7 @@ struct SmallArgs {
     bool top_from_k;      // top operator = stage operator from K (else faces)
     const T *Ktop;        // [S][n_top][n_top]
     Faces<T> f[8];        // correction faces per level (levels below top, and top if !top_from_k)
-    const double *chol;   // [S][N0][N0] lower Cholesky factor of the coarsest operator
+    const double *chol;   // [S][N0][N0] inverse of the coarsest operator (FP64)
     T *x;                 // [S][n_top^2] in/out
     const T *b;           // [S][n_top^2] rhs (array mode)
     const T *xc;          // interp source [S][(n_top/2)^2] (INIT_INTERP)
@@ -95,7 +95,8 @@ struct SmallArgs {
 template <typename T>
 int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out, hipStream_t st);
 
-// Cholesky factor of the coarsest operator (n0 x n0 grid) from K or faces.
+// Inverse of the coarsest operator (n0 x n0 grid, n0^2 <= 16) from K or faces,
+// through its Cholesky factor, in FP64.
 template <typename T>
 int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, double *L, int S, hipStream_t st);
 

@@ -41,10 +41,21 @@ __device__ __forceinline__ void store_pyramid(const KLArgs &A, int S, int s, int
     }
 }
 
-// B slice for modes [m0, m0+TM) and cells [c0, c0+TC): Bt[m][c]
+// B slice for modes [m0, m0+TM) and cells [c0, c0+TC): Bt[m][c]. When the
+// cell tile lies in one grid row j (n >= TC), rowf[m] = sqrt(lambda_m) phi_{b_m}(y_j)
+// and ia[m] = a_m * n are staged in LDS once per workgroup.
 template <typename TB>
-__device__ __forceinline__ void build_b(const KLArgs &A, int m0, int c0, TB *Bt) {
+__device__ __forceinline__ void build_b(const KLArgs &A, int m0, int c0, TB *Bt, const double *rowf,
+                                       const int *ia) {
     const int n = A.n;
+    if (rowf) {
+        const int i0 = c0 % n;
+        for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
+            const int mm = e / TC, cc = e % TC, m = m0 + mm;
+            Bt[mm * (TC + PAD) + cc] = TB((m < A.M) ? rowf[m] * A.phi[ia[m] + i0 + cc] : 0.0);
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
         const int mm = e / TC, cc = e % TC;
         const int m = m0 + mm, c = c0 + cc;
@@ -55,6 +66,18 @@ __device__ __forceinline__ void build_b(const KLArgs &A, int m0, int c0, TB *Bt)
         }
         Bt[mm * (TC + PAD) + cc] = TB(v);
     }
+}
+
+// stages rowf / ia for a one-row tile; returns whether it applies
+__device__ __forceinline__ bool stage_row(const KLArgs &A, int c0, double *rowf, int *ia) {
+    const int n = A.n;
+    if (n < TC) return false;
+    const int j = c0 / n;
+    for (int m = threadIdx.x; m < A.M; m += blockDim.x) {
+        rowf[m] = A.sqrtlam[m] * A.phi[size_t(A.mb[m]) * n + j];
+        ia[m] = A.ma[m] * n;
+    }
+    return true;
 }
 
 template <typename TA>
@@ -73,14 +96,17 @@ __device__ __forceinline__ void load_xi(const KLArgs &A, int S, int s0, int m0, 
 __global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
     __shared__ double Xs[TS * (TM + PAD)];
     __shared__ double Bt[TM * (TC + PAD)];
+    extern __shared__ double rowf[];  // [M] then int ia[M]
+    int *ia = reinterpret_cast<int *>(rowf + A.M);
     const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const bool row = stage_row(A, c0, rowf, ia);
     d4 acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     for (int m0 = 0; m0 < A.M; m0 += TM) {
         __syncthreads();
         load_xi(A, S, s0, m0, Xs);
-        build_b(A, m0, c0, Bt);
+        build_b(A, m0, c0, Bt, row ? rowf : nullptr, ia);
         __syncthreads();
 #pragma unroll 4
         for (int kk = 0; kk < TM / 4; ++kk) {
@@ -104,14 +130,17 @@ __global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
 __global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
     __shared__ float Xs[TS * (TM + PAD)];
     __shared__ float Bt[TM * (TC + PAD)];
+    extern __shared__ double rowf[];  // [M] then int ia[M]
+    int *ia = reinterpret_cast<int *>(rowf + A.M);
     const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const bool row = stage_row(A, c0, rowf, ia);
     f4 acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
     for (int m0 = 0; m0 < A.M; m0 += TM) {
         __syncthreads();
         load_xi(A, S, s0, m0, Xs);
-        build_b(A, m0, c0, Bt);
+        build_b(A, m0, c0, Bt, row ? rowf : nullptr, ia);
         __syncthreads();
 #pragma unroll 4
         for (int kk = 0; kk < TM / 4; ++kk) {
@@ -184,8 +213,9 @@ __global__ __launch_bounds__(256) void k_kl_bf16(KLArgs A, int S) {
 int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st) {
     if (S <= 0) return FMGMC_OK;
     dim3 grid((a.n * a.n + TC - 1) / TC, (S + TS - 1) / TS), block(256);
-    if (prec == FMGMC_KL_FP64) hipLaunchKernelGGL(k_kl_f64, grid, block, 0, st, a, S);
-    else if (prec == FMGMC_KL_FP32) hipLaunchKernelGGL(k_kl_f32, grid, block, 0, st, a, S);
+    const size_t dyn = size_t(a.M) * (sizeof(double) + sizeof(int));
+    if (prec == FMGMC_KL_FP64) hipLaunchKernelGGL(k_kl_f64, grid, block, dyn, st, a, S);
+    else if (prec == FMGMC_KL_FP32) hipLaunchKernelGGL(k_kl_f32, grid, block, dyn, st, a, S);
     else if (prec == FMGMC_KL_BF16) hipLaunchKernelGGL(k_kl_bf16, grid, block, 0, st, a, S);
     else {
         set_error("launch_kl: unknown precision");

@@ -3,8 +3,10 @@
 // corrections on grids n <= wmax): red-black Gauss-Seidel,
 // residual restriction by 2x2 sums, bilinear prolongation, and the direct
 // solve on the coarsest grid (Section 2.5; Cholesky factor precomputed in
-// FP64). With top == 0 the call is the coarsest-grid direct solve itself
-// (the first stage of full multigrid).
+// FP64, applied as the explicit inverse of the 16 x 16 coarsest operator,
+// built once per batch from its Cholesky factor). With top == 0 the call is the
+// coarsest-grid direct solve itself (the first stage of full multigrid).
+// One 256-lane workgroup per sample.
 #include "common.h"
 
 namespace fmgmc {
@@ -80,21 +82,14 @@ __device__ void smooth(const Lv<T> &L, int nu) {
     }
 }
 
+// coarsest solve x = A^{-1} b in FP64: one lane per unknown
 template <typename T>
-__device__ void chol_solve16(const double *Ls, int N, const T *b, T *x, double *y) {
-    // one thread: forward and back substitution in FP64
-    if (threadIdx.x == 0) {
-        for (int r = 0; r < N; ++r) {
-            double s = double(b[r]);
-            for (int k = 0; k < r; ++k) s -= Ls[r * N + k] * y[k];
-            y[r] = s / Ls[r * N + r];
-        }
-        for (int r = N - 1; r >= 0; --r) {
-            double s = y[r];
-            for (int k = r + 1; k < N; ++k) s -= Ls[k * N + r] * y[k];
-            y[r] = s / Ls[r * N + r];
-        }
-        for (int r = 0; r < N; ++r) x[r] = T(y[r]);
+__device__ void coarse_solve(const double *Ainv, int N, const T *b, T *x) {
+    if (threadIdx.x < N) {
+        const double *row = Ainv + threadIdx.x * N;
+        double s = 0.0;
+        for (int k = 0; k < N; ++k) s += row[k] * double(b[k]);
+        x[threadIdx.x] = T(s);
     }
     __syncthreads();
 }
@@ -104,55 +99,62 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     const int s = blockIdx.x;
     if (A.active && A.active[s] == 0) return;
     extern __shared__ unsigned char smem_raw[];
-    T *p = reinterpret_cast<T *>(smem_raw);
-    Lv<T> L[kMaxLev];
+    T *const base = reinterpret_cast<T *>(smem_raw);
     const int top = A.top;
-    for (int k = 0; k <= top; ++k) {
+    // level k arrays (x, b, fx, fy, id of n*n, then fxe of n), packed from level 0 up
+    auto lv = [&](int k) -> Lv<T> {
+        T *p = base;
+        for (int j = 0; j < k; ++j) p += 5 * A.ns[j] * A.ns[j] + A.ns[j];
         const int n = A.ns[k];
-        L[k].n = n;
-        L[k].x = p; p += n * n;
-        L[k].b = p; p += n * n;
-        L[k].fx = p; p += n * n;
-        L[k].fy = p; p += n * n;
-        L[k].id = p; p += n * n;
-        L[k].fxe = p; p += n;
-    }
+        Lv<T> L;
+        L.n = n;
+        L.x = p; p += n * n;
+        L.b = p; p += n * n;
+        L.fx = p; p += n * n;
+        L.fy = p; p += n * n;
+        L.id = p; p += n * n;
+        L.fxe = p;
+        return L;
+    };
+    T *p = base;
+    for (int j = 0; j <= top; ++j) p += 5 * A.ns[j] * A.ns[j] + A.ns[j];
     double *Ls = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(p) + 7) & ~uintptr_t(7));
     const int N0 = A.ns[0] * A.ns[0];
-    double *y = Ls + N0 * N0;
-    T *red = reinterpret_cast<T *>(y + N0);
+    T *red = reinterpret_cast<T *>(Ls + N0 * N0);
     const T gW = T(A.pW), gE = T(A.pE);
-
     // coefficients of every level
     for (int k = 0; k <= top; ++k) {
-        const int n = L[k].n, nn = n * n;
+        const Lv<T> Lk = lv(k);
+        const int n = Lk.n, nn = n * n;
         if (k == top && A.top_from_k) {
             const T *K = A.Ktop + size_t(s) * nn;
             for (int c = threadIdx.x; c < nn; c += blockDim.x) {
                 const int i = c % n, j = c / n;
-                L[k].fx[c] = i == 0 ? T(2) * K[c] : harm_s(K[c - 1], K[c]);
-                L[k].fy[c] = j == 0 ? T(0) : harm_s(K[c - n], K[c]);
-                if (i == n - 1) L[k].fxe[j] = T(2) * K[c];
+                Lk.fx[c] = i == 0 ? T(2) * K[c] : harm_s(K[c - 1], K[c]);
+                Lk.fy[c] = j == 0 ? T(0) : harm_s(K[c - n], K[c]);
+                if (i == n - 1) Lk.fxe[j] = T(2) * K[c];
             }
         } else {
-            const Faces<T> f = A.f[k];
+            const T *fx = A.f[k].fx + size_t(s) * nn, *fy = A.f[k].fy + size_t(s) * nn;
+            const T *fe = A.f[k].fxe + size_t(s) * n;
             for (int c = threadIdx.x; c < nn; c += blockDim.x) {
-                L[k].fx[c] = f.fx[size_t(s) * nn + c];
-                L[k].fy[c] = f.fy[size_t(s) * nn + c];
+                Lk.fx[c] = fx[c];
+                Lk.fy[c] = fy[c];
             }
-            for (int c = threadIdx.x; c < n; c += blockDim.x) L[k].fxe[c] = f.fxe[size_t(s) * n + c];
+            for (int c = threadIdx.x; c < n; c += blockDim.x) Lk.fxe[c] = fe[c];
         }
     }
     for (int c = threadIdx.x; c < N0 * N0; c += blockDim.x) Ls[c] = A.chol[size_t(s) * N0 * N0 + c];
     __syncthreads();
     for (int k = 0; k <= top; ++k) {
-        const int n = L[k].n;
+        const Lv<T> Lk = lv(k);
+        const int n = Lk.n;
         for (int c = threadIdx.x; c < n * n; c += blockDim.x)
-            L[k].id[c] = T(1) / diag(L[k], c % n, c / n);
+            Lk.id[c] = T(1) / diag(Lk, c % n, c / n);
     }
     // right-hand side and initial guess on the top level
     {
-        Lv<T> &Tp = L[top];
+        const Lv<T> Tp = lv(top);
         const int n = Tp.n, nn = n * n;
         for (int c = threadIdx.x; c < nn; c += blockDim.x) {
             const int i = c % n, j = c / n;
@@ -176,52 +178,58 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     // pre-smoothing and restriction, then cnt[k] coarse cycles (two when the
     // coarse grid is not the coarsest and has n <= wmax, a W-cycle; else one),
     // then prolongation and post-smoothing. Control flow is uniform.
-    int cnt[kMaxLev];
+    unsigned cnt = 0;  // 2 bits per level: coarse cycles still to run from that level
     int k = top;
     bool down = true;
     while (true) {
         if (down) {
             if (k == 0) {
-                chol_solve16(Ls, N0, L[0].b, L[0].x, y);
+                const Lv<T> L0 = lv(0);
+                coarse_solve(Ls, N0, L0.b, L0.x);
                 if (top == 0) break;
                 k = 1;
                 down = false;
                 continue;
             }
-            smooth(L[k], A.nu1);
-            const int n = L[k].n, nc = n / 2;
+            const Lv<T> Lk = lv(k), Lc = lv(k - 1);
+            smooth(Lk, A.nu1);
+            const int n = Lk.n, nc = n / 2;
             for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
                 const int I = c % nc, J = c / nc;
                 T acc = T(0);
                 for (int dj = 0; dj < 2; ++dj)
                     for (int di = 0; di < 2; ++di) {
                         const int i = 2 * I + di, j = 2 * J + dj;
-                        acc += nbsum(L[k], i, j) - diag(L[k], i, j) * L[k].x[j * n + i];
+                        acc += nbsum(Lk, i, j) - diag(Lk, i, j) * Lk.x[j * n + i];
                     }
-                L[k - 1].b[c] = acc;
-                L[k - 1].x[c] = T(0);
+                Lc.b[c] = acc;
+                Lc.x[c] = T(0);
             }
             __syncthreads();
-            cnt[k] = (k - 1 > 0 && L[k - 1].n <= A.wmax) ? 2 : 1;
+            const unsigned g = (k - 1 > 0 && Lc.n <= A.wmax) ? 2u : 1u;
+            cnt = (cnt & ~(3u << (2 * k))) | (g << (2 * k));
             k = k - 1;
         } else {
-            if (--cnt[k] > 0) {  // run the coarse cycle again from its current iterate
+            const unsigned left = ((cnt >> (2 * k)) & 3u) - 1u;
+            cnt = (cnt & ~(3u << (2 * k))) | (left << (2 * k));
+            if (left > 0) {  // run the coarse cycle again from its current iterate
                 k = k - 1;
                 down = true;
                 continue;
             }
-            const int n = L[k].n, nc = n / 2;
+            const Lv<T> Lk = lv(k), Lc = lv(k - 1);
+            const int n = Lk.n, nc = n / 2;
             for (int c = threadIdx.x; c < n * n; c += blockDim.x)
-                L[k].x[c] += interp_at(L[k - 1].x, nc, c % n, c / n, T(0), T(0));
+                Lk.x[c] += interp_at(Lc.x, nc, c % n, c / n, T(0), T(0));
             __syncthreads();
-            smooth(L[k], A.nu2);
+            smooth(Lk, A.nu2);
             if (k == top) break;
             k = k + 1;
         }
     }
 
     // outputs
-    Lv<T> &Tp = L[top];
+    const Lv<T> Tp = lv(top);
     const int n = Tp.n, nn = n * n;
     for (int c = threadIdx.x; c < nn; c += blockDim.x) A.x[size_t(s) * nn + c] = Tp.x[c];
     if (out & OUT_RR) {
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
 
 template <typename T>
 int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out, hipStream_t st) {
-    if (a.top < 0 || a.top >= kMaxLev || a.ns[0] * a.ns[0] > 64) {
+    if (a.top < 0 || a.top >= kMaxLev || a.ns[0] * a.ns[0] > 16) {
         set_error("launch_small: unsupported hierarchy");
         return FMGMC_EINVAL;
     }
@@ -261,7 +269,7 @@ int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out
     const int N0 = a.ns[0] * a.ns[0];
     size_t bytes = words * sizeof(T);
     bytes = (bytes + 7) & ~size_t(7);
-    bytes += (size_t(N0) * N0 + N0) * sizeof(double) + 8 * sizeof(T);
+    bytes += size_t(N0) * N0 * sizeof(double) + 8 * sizeof(T);
     hipLaunchKernelGGL(k_small<T>, dim3(S), dim3(kThreads), bytes, st, a, init, rhs_array, out);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
@@ -269,7 +277,7 @@ int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out
 template int launch_small<double>(const SmallArgs<double> &, int, int, bool, int, hipStream_t);
 template int launch_small<float>(const SmallArgs<float> &, int, int, bool, int, hipStream_t);
 
-// --------------------------------------------------------- coarsest factor
+// ------------------------------------------------- coarsest operator inverse
 template <typename T>
 __global__ void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout, int S) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,11 +325,29 @@ __global__ void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout
             L[r * N + c] = v / d;
         }
     }
+    // explicit inverse A^{-1} = L^{-T} L^{-1}: columns of L^{-1} by forward
+    // substitution into the (now unused) upper triangle workspace W
+    double W[16];  // one column of L^{-1} (N <= 16)
+    double Li[16 * 16];
+    for (int c = 0; c < N; ++c) {
+        for (int r = 0; r < N; ++r) {
+            double v = (r == c) ? 1.0 : 0.0;
+            for (int k = c; k < r; ++k) v -= L[r * N + k] * W[k];
+            W[r] = (r < c) ? 0.0 : v / L[r * N + r];
+        }
+        for (int r = 0; r < N; ++r) Li[r * N + c] = W[r];
+    }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double v = 0.0;
+            for (int k = (i > j ? i : j); k < N; ++k) v += Li[k * N + i] * Li[k * N + j];
+            L[i * N + j] = v;
+        }
 }
 
 template <typename T>
 int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, double *L, int S, hipStream_t st) {
-    if (n0 * n0 > 64) {
+    if (n0 * n0 > 16) {
         set_error("launch_chol: coarsest grid too large");
         return FMGMC_EINVAL;
     }

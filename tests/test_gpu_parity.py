@@ -67,8 +67,9 @@ def assert_same_solution(g, o, gcyc, ocyc, rel_tol, label):
 
 
 # ------------------------------------------------------------------ KL field
-@pytest.mark.parametrize("level,S", [(0, 70), (1, 33)])
+@pytest.mark.parametrize("level,S", [(0, 70), (1, 33), (3, 70)])
 def test_field_fp64_matches_oracle(level, S):
+    """32^2 and 64^2 (narrow tiles) and 256^2 (wide row tiles), ragged sample counts."""
     cfg = CFG2
     n = cfg["n0"] << level
     xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=1)
