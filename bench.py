@@ -74,6 +74,12 @@ def run_form(torch, fmgmc, xi_dev, solver, args):
                 prof=prof, qf=qf.cpu().numpy(), qc=qc.cpu().numpy())
 
 
+# Measured HBM traffic / algorithmic bytes of the dominant kernels, from the
+# rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
+# (profiles/hbm_traffic_512.md). None once a kernel changes after measurement.
+TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000}
+
+
 def roofline(form, steps):
     """Dominant HBM-bound kernel of a form from the library's event timing."""
     best = None
@@ -83,8 +89,10 @@ def roofline(form, steps):
             best = (kind, ms, n, alg)
     kind, ms, n, alg = best
     gbs = alg / (ms * 1e-3) / 1e9
+    ratio = TRAFFIC_RATIO.get(kind)
+    traffic = None if ratio is None else round(ratio * alg / n / 1e9, 4)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "GB per launch",
             "kernel": kind, "avg_launch_us": round(1e3 * ms / n, 2), "launches": n,
             "alg_bytes_per_launch": alg / n}
 
@@ -112,7 +120,7 @@ def main():
     ap.add_argument("--inner", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--forms", default="fp32_ir,fp64")
-    ap.add_argument("--cpu-samples", type=int, default=48)
+    ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")

@@ -426,7 +426,12 @@ int run_batch_ir(fmgmc_ctx *c, int level, int S, double *qf, double *qc, hipStre
         ia.active = c->active;
         ia.pW = pW;
         ia.pE = pE;
-        TRY(launch_ir(ia, S, st));
+        {
+            // first residual of the stage: reads p and K, writes r (20 B per cell)
+            const double irb0 = double(c->n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
+            if (k == c->top_grid) TRY(timed(c, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
+            else TRY(launch_ir(ia, S, st));
+        }
         const int inner = std::max(1, c->opts.inner_cycles);
         for (int done = 0; done < c->opts.max_cycles; done += inner) {
             for (int ic = 0; ic < inner; ++ic)
