@@ -138,6 +138,40 @@ int fmgmc_solve_level(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const do
                       double *q_fine, double *q_coarse, int32_t *cycles, uint8_t *flags,
                       void *stream);
 
+/*
+ * All MLMC levels of one estimate at once (Algorithm 3, the loop over levels
+ * with dN_l > 0): level l solves n_samples[l] samples with xi[l]
+ * ([n_samples[l]][n_modes]) into q_fine[l], q_coarse[l] (and cycles[l],
+ * flags[l] if those tables and entries are non-NULL), as fmgmc_solve_level
+ * would. The levels run concurrently, each on its own stream and device
+ * workspace (allocated on first use: the finest-level workspace's memory
+ * budget per level), so small grids overlap the large ones. Results are
+ * identical to per-level fmgmc_solve_level calls. `stream` is synchronised
+ * first (inputs may be produced on it); the call returns when every level is
+ * done. Returns as fmgmc_solve_level, over all levels.
+ */
+int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples,
+                       const double *const *xi, double *const *q_fine,
+                       double *const *q_coarse, int32_t *const *cycles,
+                       uint8_t *const *flags, void *stream);
+
+/*
+ * Schedule of one level: params[0] = cycles per host check of convergence
+ * (G >= 1; a converged sample still stops after its own cycle because every
+ * cycle is followed by the on-device check), params[1] = replay each block of
+ * G cycles from a captured HIP graph (0/1; blocks on the null stream always
+ * run eagerly), params[2] = samples per device chunk (0 = workspace capacity).
+ * A schedule never changes results.
+ *
+ * fmgmc_autotune measures every schedule in {1,2,4,8} x {eager, graph} x
+ * {capacity, 1/2, 1/4} on n_pilot samples of level `level` (xi host or
+ * device), keeps the fastest for that level and writes it to params (nullable,
+ * 3 entries). fmgmc_set_schedule sets it directly.
+ */
+int fmgmc_autotune(fmgmc_ctx *ctx, int32_t level, int64_t n_pilot, const double *xi,
+                   int32_t *params);
+int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params);
+
 /* Per-level statistics filled by fmgmc_estimate. */
 typedef struct {
     int64_t n;        /* samples */

@@ -4,23 +4,35 @@
 // samples:
 //   1. KL synthesis (matrix cores) -> injected coefficient pyramid;
 //   2. correction-operator pyramids (face averaging) for the two QoI stages
-//      and the Cholesky factors of the coarsest operators;
+//      and the FP64 inverses of the coarsest operators;
 //   3. full multigrid: direct solve on the coarsest grid, then for each finer
-//      grid an interpolated start and V(nu1,nu2) cycles - one per
-//      intermediate stage, and until ||b - A p|| <= tol ||b|| on the stages
-//      n_l/2 (gives Q^c_l) and n_l (gives Q^f_l). Converged samples drop out
-//      of every later launch through a per-sample activity mask.
+//      grid an interpolated start and cycles - one per intermediate stage, and
+//      until ||b - A p|| <= tol ||b|| on the stages n_l/2 (gives Q^c_l) and n_l
+//      (gives Q^f_l). Converged samples drop out of every later launch through
+//      a per-sample activity mask.
 //   FP32_IR: cycles in FP32; on the QoI stages FP64 iterative refinement
 //   (p64 += e32, r = b - A64 p64) decides convergence and yields the QoI.
+//
+// Scheduling: after the first cycle of a QoI stage, cycles run in blocks of G
+// (cycle + convergence check each); the host reads the number of samples still
+// iterating once per block. A block can be captured once into a HIP graph and
+// replayed. Several MLMC levels can run at once, each on its own stream and
+// workspace (fmgmc_solve_levels). G, graph use and the batch size per level
+// come from a measured autotuner (fmgmc_autotune). None of these choices
+// changes any result: the same kernels run on the same samples in the same order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -32,8 +44,8 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 namespace {
 
-constexpr int kMaxGrid = 8;   // grid indices 0..7: 4 .. 512 (n_coarsest = 4) or up to 1024
-constexpr int kSmallTop = 32; // grids up to this size run whole cycles in LDS
+constexpr int kMaxGrid = 9;    // grid indices: n_coarsest << k
+constexpr int kSmallTop = 32;  // grids up to this size run whole cycles in LDS
 
 int ilog2(int v) {
     int r = 0;
@@ -74,6 +86,62 @@ struct Pyr {
     Faces<T> f[kMaxGrid];
 };
 
+#define TRY(x)                           \
+    do {                                 \
+        int rc_ = (x);                   \
+        if (rc_ != FMGMC_OK) return rc_; \
+    } while (0)
+
+// Schedule parameters of one MLMC level (never change results).
+struct Tune {
+    int check_every = 1;   // cycles per host read of the active count
+    int graphs = 0;        // replay the cycle block from a captured HIP graph
+    int batch = 0;         // samples per device chunk (0 = workspace capacity)
+};
+
+// Device buffers for a batch of up to S_max samples of one hierarchy.
+struct Work {
+    int S_max = 0;
+    int ng = 0;                       // grid levels 0..ng-1
+    int nsz[kMaxGrid] = {};
+    double *K64[kMaxGrid] = {};
+    float *K32[kMaxGrid] = {};
+    double *x64[kMaxGrid] = {}, *b64[kMaxGrid] = {}, *p64[kMaxGrid] = {};
+    float *x32[kMaxGrid] = {}, *b32[kMaxGrid] = {};
+    Pyr<double> pf64[2];
+    Pyr<float> pf32[2];
+    double *chol = nullptr;  // [3][S][N0*N0]: inverses of stage op, coarse-stage pyramid, fine-stage pyramid
+    double *rr = nullptr, *q = nullptr, *bnorm = nullptr, *qf = nullptr, *qc = nullptr, *xi = nullptr;
+    int32_t *active = nullptr, *cycles = nullptr, *n_active = nullptr;
+    uint8_t *flags = nullptr;
+    int32_t *h_n_active = nullptr;  // pinned
+    int n_active_host = 0;
+    int top_grid = -1;
+    bool profile = false;           // profiling records allowed for this workspace
+    hipStream_t own_stream = nullptr;
+    // captured cycle blocks, keyed by (MLMC level, stage grid, block length, batch size)
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+};
+
+void free_work(Work &w) {
+    for (int k = 0; k < kMaxGrid; ++k) {
+        dfree(w.K64[k]); dfree(w.K32[k]); dfree(w.x64[k]); dfree(w.b64[k]); dfree(w.p64[k]);
+        dfree(w.x32[k]); dfree(w.b32[k]);
+        for (int q = 0; q < 2; ++q) {
+            dfree(w.pf64[q].f[k].fx); dfree(w.pf64[q].f[k].fy); dfree(w.pf64[q].f[k].fxe);
+            dfree(w.pf32[q].f[k].fx); dfree(w.pf32[q].f[k].fy); dfree(w.pf32[q].f[k].fxe);
+        }
+    }
+    dfree(w.chol); dfree(w.rr); dfree(w.q); dfree(w.bnorm); dfree(w.qf); dfree(w.qc); dfree(w.xi);
+    dfree(w.active); dfree(w.cycles); dfree(w.n_active); dfree(w.flags);
+    if (w.h_n_active) (void)hipHostFree(w.h_n_active);
+    w.h_n_active = nullptr;
+    for (auto &kv : w.graphs) (void)hipGraphExecDestroy(kv.second);
+    w.graphs.clear();
+    if (w.own_stream) (void)hipStreamDestroy(w.own_stream);
+    w.own_stream = nullptr;
+}
+
 }  // namespace
 }  // namespace fmgmc
 
@@ -85,29 +153,14 @@ struct fmgmc_ctx {
     fmgmc_opts opts;
     int device = 0;
     ModeTable table;
-    int S_max = 0;
-    int ng = 0;   // grid levels of the finest MLMC level (indices 0..ng-1)
-    int nsz[kMaxGrid] = {};
-    int small_top = 0;  // largest grid index handled by the LDS kernel
-
+    int small_top = 0;   // largest grid index handled by the LDS kernel
     // constants
     std::vector<double *> d_phi;  // per MLMC level [kmax+1][n_l]
     int32_t *d_ma = nullptr, *d_mb = nullptr;
     double *d_sqrtlam = nullptr;
-
-    // batch buffers (index = grid level)
-    double *K64[kMaxGrid] = {};
-    float *K32[kMaxGrid] = {};
-    double *x64[kMaxGrid] = {}, *b64[kMaxGrid] = {}, *p64[kMaxGrid] = {};
-    float *x32[kMaxGrid] = {}, *b32[kMaxGrid] = {};
-    Pyr<double> pf64[2];
-    Pyr<float> pf32[2];
-    double *chol = nullptr;  // [3][S][N0*N0]: stage operator, coarse-stage pyramid, fine-stage pyramid
-    double *rr = nullptr, *q = nullptr, *bnorm = nullptr, *qf = nullptr, *qc = nullptr, *xi = nullptr;
-    int32_t *active = nullptr, *cycles = nullptr, *n_active = nullptr;
-    uint8_t *flags = nullptr;
-    int32_t *h_n_active = nullptr;  // pinned
-    double *red_scratch = nullptr;
+    Work main;                                  // finest-level workspace (fmgmc_solve_level)
+    std::vector<std::unique_ptr<Work>> lev;     // per-level workspaces (fmgmc_solve_levels)
+    std::vector<Tune> tune;                     // per MLMC level
     // measurement hooks
     struct Rec {
         hipEvent_t a, b;
@@ -115,37 +168,11 @@ struct fmgmc_ctx {
     };
     bool prof = false;
     std::vector<Rec> prof_rec[FMGMC_PROF_KINDS];
-    int top_grid = -1;   // grid index of the finest grid of the solve in progress
-    int n_active_host = 0;
 };
 
 namespace {
 
 bool ir_mode(const fmgmc_ctx *c) { return c->opts.solver == FMGMC_SOLVER_FP32_IR; }
-
-void free_all(fmgmc_ctx *c) {
-    for (auto &p : c->d_phi) dfree(p);
-    c->d_phi.clear();
-    dfree(c->d_ma); dfree(c->d_mb); dfree(c->d_sqrtlam);
-    for (int k = 0; k < kMaxGrid; ++k) {
-        dfree(c->K64[k]); dfree(c->K32[k]); dfree(c->x64[k]); dfree(c->b64[k]); dfree(c->p64[k]);
-        dfree(c->x32[k]); dfree(c->b32[k]);
-        for (int q = 0; q < 2; ++q) {
-            dfree(c->pf64[q].f[k].fx); dfree(c->pf64[q].f[k].fy); dfree(c->pf64[q].f[k].fxe);
-            dfree(c->pf32[q].f[k].fx); dfree(c->pf32[q].f[k].fy); dfree(c->pf32[q].f[k].fxe);
-        }
-    }
-    dfree(c->chol); dfree(c->rr); dfree(c->q); dfree(c->bnorm); dfree(c->qf); dfree(c->qc); dfree(c->xi);
-    dfree(c->active); dfree(c->cycles); dfree(c->n_active); dfree(c->flags); dfree(c->red_scratch);
-    if (c->h_n_active) (void)hipHostFree(c->h_n_active);
-    c->h_n_active = nullptr;
-}
-
-#define TRY(x)                          \
-    do {                                \
-        int rc_ = (x);                  \
-        if (rc_ != FMGMC_OK) return rc_; \
-    } while (0)
 
 template <typename T>
 int alloc_faces(Faces<T> &f, int S, int n) {
@@ -155,46 +182,52 @@ int alloc_faces(Faces<T> &f, int S, int n) {
     return FMGMC_OK;
 }
 
-int allocate(fmgmc_ctx *c) {
-    const int S = c->S_max, M = c->table.M;
-    const int t = c->ng - 1;
+// Workspace for S samples of a hierarchy whose finest grid is n_top.
+int alloc_work(const fmgmc_ctx *c, Work &w, int S, int n_top) {
+    const int M = c->table.M;
     const bool ir = ir_mode(c);
+    w.S_max = S;
+    w.ng = ilog2(n_top / c->hier.n_coarsest) + 1;
+    for (int k = 0; k < w.ng; ++k) w.nsz[k] = c->hier.n_coarsest << k;
+    const int t = w.ng - 1;
     for (int k = 0; k <= t; ++k) {
-        const size_t N = size_t(S) * c->nsz[k] * c->nsz[k];
+        const size_t N = size_t(S) * w.nsz[k] * w.nsz[k];
         if (!ir) {
-            TRY(dalloc(&c->K64[k], N));
-            TRY(dalloc(&c->x64[k], N));
-            TRY(dalloc(&c->b64[k], N));
+            TRY(dalloc(&w.K64[k], N));
+            TRY(dalloc(&w.x64[k], N));
+            TRY(dalloc(&w.b64[k], N));
         } else {
-            TRY(dalloc(&c->K32[k], N));
-            TRY(dalloc(&c->x32[k], N));
-            TRY(dalloc(&c->b32[k], N));
-            // FP64 operator and iterate only where a QoI stage can sit
-            if (k >= 1) {
-                TRY(dalloc(&c->K64[k], N));
-                TRY(dalloc(&c->p64[k], N));
+            TRY(dalloc(&w.K32[k], N));
+            TRY(dalloc(&w.x32[k], N));
+            TRY(dalloc(&w.b32[k], N));
+            if (k >= 1) {  // FP64 operator and iterate only where a QoI stage can sit
+                TRY(dalloc(&w.K64[k], N));
+                TRY(dalloc(&w.p64[k], N));
             }
         }
         if (k < t) {
             for (int q = 0; q < 2; ++q) {
                 if (q == 0 && k >= t - 1) continue;  // coarse-stage pyramid stops below n_l / 2
-                if (!ir) TRY(alloc_faces(c->pf64[q].f[k], S, c->nsz[k]));
-                else TRY(alloc_faces(c->pf32[q].f[k], S, c->nsz[k]));
+                if (!ir) TRY(alloc_faces(w.pf64[q].f[k], S, w.nsz[k]));
+                else TRY(alloc_faces(w.pf32[q].f[k], S, w.nsz[k]));
             }
         }
     }
-    const int N0 = c->nsz[0] * c->nsz[0];
-    TRY(dalloc(&c->chol, size_t(3) * S * N0 * N0));
-    TRY(dalloc(&c->rr, S)); TRY(dalloc(&c->q, S)); TRY(dalloc(&c->bnorm, S));
-    TRY(dalloc(&c->qf, S)); TRY(dalloc(&c->qc, S)); TRY(dalloc(&c->xi, size_t(S) * M));
-    TRY(dalloc(&c->active, S)); TRY(dalloc(&c->cycles, 2 * size_t(S))); TRY(dalloc(&c->n_active, 1));
-    TRY(dalloc(&c->flags, S));
-    TRY(dalloc(&c->red_scratch, 4096));
-    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_n_active), sizeof(int32_t)) != hipSuccess) {
+    const int N0 = w.nsz[0] * w.nsz[0];
+    TRY(dalloc(&w.chol, size_t(3) * S * N0 * N0));
+    TRY(dalloc(&w.rr, S)); TRY(dalloc(&w.q, S)); TRY(dalloc(&w.bnorm, S));
+    TRY(dalloc(&w.qf, S)); TRY(dalloc(&w.qc, S)); TRY(dalloc(&w.xi, size_t(S) * M));
+    TRY(dalloc(&w.active, S)); TRY(dalloc(&w.cycles, 2 * size_t(S))); TRY(dalloc(&w.n_active, 1));
+    TRY(dalloc(&w.flags, S));
+    if (hipHostMalloc(reinterpret_cast<void **>(&w.h_n_active), sizeof(int32_t)) != hipSuccess) {
         set_error("hipHostMalloc failed");
         return FMGMC_ENOMEM;
     }
-    // tables
+    return FMGMC_OK;
+}
+
+int alloc_constants(fmgmc_ctx *c) {
+    const int M = c->table.M;
     const int nk = c->table.kmax + 1;
     TRY(dalloc(&c->d_ma, M)); TRY(dalloc(&c->d_mb, M)); TRY(dalloc(&c->d_sqrtlam, M));
     std::vector<double> sl(M);
@@ -213,11 +246,21 @@ int allocate(fmgmc_ctx *c) {
     return FMGMC_OK;
 }
 
+void free_ctx(fmgmc_ctx *c) {
+    for (auto &p : c->d_phi) dfree(p);
+    c->d_phi.clear();
+    dfree(c->d_ma); dfree(c->d_mb); dfree(c->d_sqrtlam);
+    free_work(c->main);
+    for (auto &w : c->lev)
+        if (w) free_work(*w);
+    c->lev.clear();
+}
+
 // ------------------------------------------------------------ measurement
-// Brackets one launch with events when profiling is on.
+// Brackets one launch with events when profiling is on (never inside a capture).
 template <typename F>
-int timed(fmgmc_ctx *c, int kind, double alg, hipStream_t st, F &&launch) {
-    if (!c->prof) return launch();
+int timed(fmgmc_ctx *c, Work &w, int kind, double alg, hipStream_t st, F &&launch) {
+    if (!c->prof || !w.profile) return launch();
     fmgmc_ctx::Rec r{nullptr, nullptr, alg};
     FMGMC_HIP(hipEventCreate(&r.a));
     FMGMC_HIP(hipEventCreate(&r.b));
@@ -235,36 +278,36 @@ struct Bufs {
     Pyr<T> *pf;
 };
 
-Bufs<double> bufs64(fmgmc_ctx *c) { return {c->K64, c->x64, c->b64, c->pf64}; }
-Bufs<float> bufs32(fmgmc_ctx *c) { return {c->K32, c->x32, c->b32, c->pf32}; }
+Bufs<double> bufs64(Work &w) { return {w.K64, w.x64, w.b64, w.pf64}; }
+Bufs<float> bufs32(Work &w) { return {w.K32, w.x32, w.b32, w.pf32}; }
 
 // One cycle with top grid k: top operator from K (stage operator), the levels
 // below from correction pyramid q; V(nu1,nu2) on grids above w_max_n, two
 // coarse cycles (W) on grids n <= w_max_n. rhs_array: top rhs in b[k] (else the
 // Dirichlet data). init: INIT_ZERO / INIT_LOAD / INIT_INTERP (from x[k-1]).
 template <typename T>
-int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_array, int out_top,
+int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool rhs_array, int out_top,
            hipStream_t st) {
     const int nh1 = 2 * c->opts.nu1, nh2 = 2 * c->opts.nu2;
-    const int N0 = c->nsz[0] * c->nsz[0];
+    const int N0 = W.nsz[0] * W.nsz[0];
     const double pW = c->hier.p_west, pE = c->hier.p_east;
-    const double *chol_pyr = c->chol + size_t(1 + q) * S * N0 * N0;
-    const double *chol_stage = c->chol;
-    auto gamma = [&](int j) { return (j > 0 && c->nsz[j] <= c->opts.w_max_n) ? 2 : 1; };
+    const double *chol_pyr = W.chol + size_t(1 + q) * S * N0 * N0;
+    const double *chol_stage = W.chol;
+    auto gamma = [&](int j) { return (j > 0 && W.nsz[j] <= c->opts.w_max_n) ? 2 : 1; };
     auto small = [&](int top, bool from_k, int sinit, bool srhs, int sout, const double *chol) {
         SmallArgs<T> a{};
         a.top = top;
-        for (int j = 0; j <= top; ++j) a.ns[j] = c->nsz[j];
+        for (int j = 0; j <= top; ++j) a.ns[j] = W.nsz[j];
         a.top_from_k = from_k;
         a.Ktop = B.K[top];
-        for (int j = 0; j < kMaxGrid; ++j) a.f[j] = B.pf[q].f[j];
+        for (int j = 0; j < 8; ++j) a.f[j] = B.pf[q].f[j];
         a.chol = chol;
         a.x = B.x[top];
         a.b = B.b[top];
         a.xc = top > 0 ? B.x[top - 1] : nullptr;
-        a.rr = c->rr;
-        a.q = c->q;
-        a.active = c->active;
+        a.rr = W.rr;
+        a.q = W.q;
+        a.active = W.active;
         a.pW = pW;
         a.pE = pE;
         a.nu1 = c->opts.nu1;
@@ -278,16 +321,16 @@ int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_arra
     }
     auto march = [&](int j, bool ck, int minit, bool rhsa, int mout, int nh) {
         MarchArgs<T> a{};
-        a.n = c->nsz[j];
+        a.n = W.nsz[j];
         a.x = B.x[j];
         a.b = B.b[j];
         a.K = B.K[j];
         a.f = B.pf[q].f[j];
         a.xc = B.x[j - 1];
         a.bc = B.b[j - 1];
-        a.rr = c->rr;
-        a.q = c->q;
-        a.active = c->active;
+        a.rr = W.rr;
+        a.q = W.q;
+        a.active = W.active;
         a.pW = pW;
         a.pE = pE;
         return launch_march(a, S, nh, ck, minit, rhsa, mout, st);
@@ -300,150 +343,211 @@ int vcycle(fmgmc_ctx *c, Bufs<T> B, int S, int k, int q, int init, bool rhs_arra
         return march(j, false, INIT_PROLONG, true, 0, nh2);
     };
     // algorithmic bytes per cell of the top-grid passes (each operand once)
-    const double w = sizeof(T), cells = double(c->nsz[k]) * c->nsz[k];
-    const bool top = (k == c->top_grid);
-    const double act = double(c->n_active_host);
+    const double w = sizeof(T), cells = double(W.nsz[k]) * W.nsz[k];
+    const bool top = (k == W.top_grid);
+    const double act = double(W.n_active_host);
     const double b_pre = (init == INIT_ZERO ? 0.0 : (init == INIT_INTERP ? 0.25 * w : w)) + w /*K*/ +
                          (rhs_array ? w : 0.0) + w /*x out*/ + 0.25 * w /*restricted residual*/;
     const double b_post = w + 0.25 * w + w + (rhs_array ? w : 0.0) + w;
-    if (top) TRY(timed(c, FMGMC_PROF_PRE, act * cells * b_pre, st, [&] { return march(k, true, init, rhs_array, OUT_RESTRICT, nh1); }));
+    if (top) TRY(timed(c, W, FMGMC_PROF_PRE, act * cells * b_pre, st, [&] { return march(k, true, init, rhs_array, OUT_RESTRICT, nh1); }));
     else TRY(march(k, true, init, rhs_array, OUT_RESTRICT, nh1));
     for (int g = 0; g < gamma(k - 1); ++g) TRY(corr(k - 1, g == 0 ? INIT_ZERO : INIT_LOAD));
-    if (top) TRY(timed(c, FMGMC_PROF_POST, act * cells * b_post, st, [&] { return march(k, true, INIT_PROLONG, rhs_array, out_top, nh2); }));
+    if (top) TRY(timed(c, W, FMGMC_PROF_POST, act * cells * b_post, st, [&] { return march(k, true, INIT_PROLONG, rhs_array, out_top, nh2); }));
     else TRY(march(k, true, INIT_PROLONG, rhs_array, out_top, nh2));
     return FMGMC_OK;
 }
 
-int read_active(fmgmc_ctx *c, hipStream_t st, int *out) {
-    FMGMC_HIP(hipMemcpyAsync(c->h_n_active, c->n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+int read_active(Work &W, hipStream_t st, int *out) {
+    FMGMC_HIP(hipMemcpyAsync(W.h_n_active, W.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FMGMC_HIP(hipStreamSynchronize(st));
-    *out = *c->h_n_active;
-    c->n_active_host = *out;
+    *out = *W.h_n_active;
+    W.n_active_host = *out;
     return FMGMC_OK;
 }
 
-int check(fmgmc_ctx *c, int S, int slot, double *qout, int inc, double tol, hipStream_t st, int *n_active) {
+int launch_checks(fmgmc_ctx *c, Work &W, int S, int slot, double *qout, int inc, double tol, hipStream_t st) {
     CheckArgs a{};
-    a.rr = c->rr;
-    a.bnorm = c->bnorm;
-    a.q = c->q;
-    a.active = c->active;
-    a.cycles = c->cycles;
+    a.rr = W.rr;
+    a.bnorm = W.bnorm;
+    a.q = W.q;
+    a.active = W.active;
+    a.cycles = W.cycles;
     a.slot = slot;
     a.inc = inc;
-    a.flags = c->flags;
+    a.flags = W.flags;
     a.qout = qout;
     a.tol = tol;
     a.max_cycles = c->opts.max_cycles;
-    a.n_active = c->n_active;
-    TRY(launch_check(a, S, st));
-    return read_active(c, st, n_active);
+    a.n_active = W.n_active;
+    return launch_check(a, S, st);
 }
 
-// Build pyramids and coarsest factors for a batch.
+// Runs `block` (G cycles + checks) eagerly or from a captured graph. The graph
+// is captured on its first use for a (level, stage grid, block length, batch
+// size) key and replayed afterwards; it holds kernel launches only, whose
+// arguments are workspace addresses and per-context constants.
+int run_block(Work &W, bool use_graph, std::tuple<int, int, int, int> key, hipStream_t st,
+              const std::function<int()> &block) {
+    if (!use_graph || st == nullptr) return block();  // no capture on the null stream
+    auto it = W.graphs.find(key);
+    if (it == W.graphs.end()) {
+        hipGraph_t g = nullptr;
+        FMGMC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int rc = block();
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc != FMGMC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            return FMGMC_EHIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+            return FMGMC_EHIP;
+        }
+        it = W.graphs.emplace(key, ex).first;
+    }
+    FMGMC_HIP(hipGraphLaunch(it->second, st));
+    return FMGMC_OK;
+}
+
+// Build correction pyramids and coarsest inverses for a batch.
 template <typename T>
-int prepare(fmgmc_ctx *c, Bufs<T> B, int S, int level, int t, hipStream_t st) {
-    const int N0 = c->nsz[0] * c->nsz[0];
+int prepare(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int level, int t, hipStream_t st) {
+    (void)c;
+    const int N0 = W.nsz[0] * W.nsz[0];
     Faces<T> none{};
-    TRY(launch_chol<T>(c->nsz[0], B.K[0], none, true, c->chol, S, st));
+    TRY(launch_chol<T>(W.nsz[0], B.K[0], none, true, W.chol, S, st));
     for (int q = 0; q < 2; ++q) {
-        const int top = (q == 1) ? t : t - 1;   // QoI stage that owns the pyramid
-        if (q == 0 && (level == 0 || top < 1)) continue;
+        const int top = (q == 1) ? t : t - 1;  // QoI stage that owns the pyramid
+        if (q == 0 && level == 0) continue;
         if (top < 1) continue;
-        TRY(launch_faces_from_k<T>(c->nsz[top], B.K[top], B.pf[q].f[top - 1], S, st));
+        TRY(launch_faces_from_k<T>(W.nsz[top], B.K[top], B.pf[q].f[top - 1], S, st));
         for (int j = top - 1; j >= 1; --j)
-            TRY(launch_faces_coarsen<T>(c->nsz[j], B.pf[q].f[j], B.pf[q].f[j - 1], S, st));
-        TRY(launch_chol<T>(c->nsz[0], nullptr, B.pf[q].f[0], false, c->chol + size_t(1 + q) * S * N0 * N0, S, st));
+            TRY(launch_faces_coarsen<T>(W.nsz[j], B.pf[q].f[j], B.pf[q].f[j - 1], S, st));
+        TRY(launch_chol<T>(W.nsz[0], nullptr, B.pf[q].f[0], false, W.chol + size_t(1 + q) * S * N0 * N0, S, st));
     }
     return FMGMC_OK;
 }
 
-int run_batch_fp64(fmgmc_ctx *c, int level, int S, double *qf, double *qc, hipStream_t st) {
-    const int t = ilog2((c->hier.n0 << level) / c->nsz[0]);
-    Bufs<double> B = bufs64(c);
-    TRY(prepare<double>(c, B, S, level, t, st));
+// Cycles of one QoI stage after its first: blocks of G (cycle + check) with one
+// host read per block, until no sample is left or max_cycles is reached.
+int iterate_stage(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int k, int S, int per_cycle, int na,
+                  hipStream_t st,
+                  const std::function<int()> &cycle_and_check) {
+    const int G = std::max(1, tn.check_every);
+    int done = per_cycle;
+    while (na > 0 && done < c->opts.max_cycles) {
+        const int g = std::min(G, (c->opts.max_cycles - done + per_cycle - 1) / per_cycle);
+        const bool graph = tn.graphs && !(c->prof && W.profile);
+        TRY(run_block(W, graph, std::make_tuple(level, k, g, S), st, [&]() -> int {
+            for (int i = 0; i < g; ++i) TRY(cycle_and_check());
+            return FMGMC_OK;
+        }));
+        TRY(read_active(W, st, &na));
+        done += g * per_cycle;
+    }
+    return FMGMC_OK;
+}
+
+int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double *qf, double *qc,
+                   hipStream_t st) {
+    const int t = ilog2((c->hier.n0 << level) / W.nsz[0]);
+    Bufs<double> B = bufs64(W);
+    TRY(prepare<double>(c, W, B, S, level, t, st));
     const double tol = c->opts.rel_tol;
     for (int k = 0; k <= t; ++k) {
         const bool fine = (k == t), coarse = (level >= 1 && k == t - 1);
         const int q = (level >= 1 && k <= t - 1) ? 0 : 1;
-        TRY(launch_fill_i32(c->active, 1, S, st));
-        c->n_active_host = S;
+        TRY(launch_fill_i32(W.active, 1, S, st));
+        W.n_active_host = S;
         if (!(fine || coarse)) {
-            TRY(vcycle<double>(c, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
+            TRY(vcycle<double>(c, W, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
             continue;
         }
         double *qout = fine ? qf : qc;
         const int slot = fine ? 1 : 0;
-        TRY(launch_bnorm<double>(c->nsz[k], B.K[k], c->hier.p_west, c->hier.p_east, c->bnorm, S, st));
+        TRY(launch_bnorm<double>(W.nsz[k], B.K[k], c->hier.p_west, c->hier.p_east, W.bnorm, S, st));
+        int na;
         if (k == 0) {  // direct solve: exact, no cycles
-            TRY(vcycle<double>(c, B, S, 0, q, INIT_ZERO, false, OUT_RR | OUT_Q, st));
-            int na;
-            TRY(check(c, S, slot, qout, 0, INFINITY, st, &na));
+            TRY(vcycle<double>(c, W, B, S, 0, q, INIT_ZERO, false, OUT_RR | OUT_Q, st));
+            TRY(launch_checks(c, W, S, slot, qout, 0, INFINITY, st));
+            TRY(read_active(W, st, &na));
             continue;
         }
-        for (int cyc = 0; cyc < c->opts.max_cycles; ++cyc) {
-            TRY(vcycle<double>(c, B, S, k, q, cyc == 0 ? INIT_INTERP : INIT_LOAD, false, OUT_RR | OUT_Q, st));
-            int na;
-            TRY(check(c, S, slot, qout, 1, tol, st, &na));
-            if (na == 0) break;
-        }
+        TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st));
+        TRY(launch_checks(c, W, S, slot, qout, 1, tol, st));
+        TRY(read_active(W, st, &na));
+        TRY(iterate_stage(c, W, tn, level, k, S, 1, na, st, [&]() -> int {
+            TRY(vcycle<double>(c, W, B, S, k, q, INIT_LOAD, false, OUT_RR | OUT_Q, st));
+            return launch_checks(c, W, S, slot, qout, 1, tol, st);
+        }));
     }
     return FMGMC_OK;
 }
 
-int run_batch_ir(fmgmc_ctx *c, int level, int S, double *qf, double *qc, hipStream_t st) {
-    const int t = ilog2((c->hier.n0 << level) / c->nsz[0]);
-    Bufs<float> B = bufs32(c);
-    TRY(prepare<float>(c, B, S, level, t, st));
+int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double *qf, double *qc,
+                 hipStream_t st) {
+    const int t = ilog2((c->hier.n0 << level) / W.nsz[0]);
+    Bufs<float> B = bufs32(W);
+    TRY(prepare<float>(c, W, B, S, level, t, st));
     const double tol = c->opts.rel_tol;
     const double pW = c->hier.p_west, pE = c->hier.p_east;
     for (int k = 0; k <= t; ++k) {
         const bool fine = (k == t), coarse = (level >= 1 && k == t - 1);
         const int q = (level >= 1 && k <= t - 1) ? 0 : 1;
-        TRY(launch_fill_i32(c->active, 1, S, st));
-        c->n_active_host = S;
+        TRY(launch_fill_i32(W.active, 1, S, st));
+        W.n_active_host = S;
         if (!(fine || coarse)) {
-            TRY(vcycle<float>(c, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
+            TRY(vcycle<float>(c, W, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
             continue;
         }
         double *qout = fine ? qf : qc;
         const int slot = fine ? 1 : 0;
-        const int n = c->nsz[k];
+        const int n = W.nsz[k];
         // FMG start in FP64
         if (fine && level >= 1)
-            TRY(launch_interp64<double>(n, c->p64[k - 1], c->p64[k], c->active, pW, pE, S, st));
+            TRY(launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, pW, pE, S, st));
         else
-            TRY(launch_interp64<float>(n, c->x32[k - 1], c->p64[k], c->active, pW, pE, S, st));
-        TRY(launch_bnorm<double>(n, c->K64[k], pW, pE, c->bnorm, S, st));
+            TRY(launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, pW, pE, S, st));
+        TRY(launch_bnorm<double>(n, W.K64[k], pW, pE, W.bnorm, S, st));
         IRArgs ia{};
         ia.n = n;
-        ia.p = c->p64[k];
+        ia.p = W.p64[k];
         ia.e = nullptr;
-        ia.K = c->K64[k];
-        ia.r32 = c->b32[k];
-        ia.rr = c->rr;
-        ia.q = c->q;
-        ia.active = c->active;
+        ia.K = W.K64[k];
+        ia.r32 = W.b32[k];
+        ia.rr = W.rr;
+        ia.q = W.q;
+        ia.active = W.active;
         ia.pW = pW;
         ia.pE = pE;
         {
             // first residual of the stage: reads p and K, writes r (20 B per cell)
-            const double irb0 = double(c->n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
-            if (k == c->top_grid) TRY(timed(c, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
+            const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
+            if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
             else TRY(launch_ir(ia, S, st));
         }
         const int inner = std::max(1, c->opts.inner_cycles);
-        for (int done = 0; done < c->opts.max_cycles; done += inner) {
+        auto step = [&]() -> int {
             for (int ic = 0; ic < inner; ++ic)
-                TRY(vcycle<float>(c, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st));
-            ia.e = c->x32[k];
-            const double irb = double(c->n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
-            if (k == c->top_grid) TRY(timed(c, FMGMC_PROF_IR, irb, st, [&] { return launch_ir(ia, S, st); }));
-            else TRY(launch_ir(ia, S, st));
-            int na;
-            TRY(check(c, S, slot, qout, inner, tol, st, &na));
-            if (na == 0) break;
-        }
+                TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st));
+            IRArgs iu = ia;
+            iu.e = W.x32[k];
+            const double irb = double(W.n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
+            if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb, st, [&] { return launch_ir(iu, S, st); }));
+            else TRY(launch_ir(iu, S, st));
+            return launch_checks(c, W, S, slot, qout, inner, tol, st);
+        };
+        int na;
+        TRY(step());
+        TRY(read_active(W, st, &na));
+        TRY(iterate_stage(c, W, tn, level, k, S, inner, na, st, step));
     }
     return FMGMC_OK;
 }
@@ -457,7 +561,6 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
     if (h->n_levels < 1 || !pow2(h->n0) || h->n_coarsest != 4 || h->n0 < h->n_coarsest) return FMGMC_EINVAL;
     const int nf = h->n0 << (h->n_levels - 1);
     if (nf > 1024) return FMGMC_EINVAL;
-    if (h->n_levels > 1 && h->n0 < 4) return FMGMC_EINVAL;
     if (o->solver != FMGMC_SOLVER_FP64 && o->solver != FMGMC_SOLVER_FP32_IR) return FMGMC_EINVAL;
     if (o->kl_prec < FMGMC_KL_FP64 || o->kl_prec > FMGMC_KL_BF16) return FMGMC_EINVAL;
     if (o->nu1 < 1 || o->nu1 > 2 || o->nu2 < 1 || o->nu2 > 2 || o->max_cycles < 1 || !(o->rel_tol > 0))
@@ -478,13 +581,112 @@ struct DevGuard {
     }
 };
 
+// One MLMC level on workspace W: chunks of at most tn.batch samples.
+int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n_samples, const double *xi,
+                   double *q_fine, double *q_coarse, int32_t *cycles, uint8_t *flags, hipStream_t st,
+                   bool *any_notconv, bool *any_nonfinite) {
+    const int M = ctx->table.M;
+    const int n = ctx->hier.n0 << level;
+    const int t = ilog2(n / W.nsz[0]);
+    const bool ir = ir_mode(ctx);
+    const bool xi_dev = is_device_ptr(xi), qf_dev = is_device_ptr(q_fine), qc_dev = is_device_ptr(q_coarse);
+    const bool cy_dev = cycles && is_device_ptr(cycles), fl_dev = flags && is_device_ptr(flags);
+    const int chunk = (tn.batch > 0 && tn.batch < W.S_max) ? tn.batch : W.S_max;
+    std::vector<uint8_t> hflags;
+    for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
+        const int S = int(std::min<int64_t>(chunk, n_samples - s0));
+        const double *x = xi + size_t(s0) * M;
+        if (!xi_dev) {
+            FMGMC_HIP(hipMemcpyAsync(W.xi, x, size_t(S) * M * sizeof(double), hipMemcpyHostToDevice, st));
+            x = W.xi;
+        }
+        // the batch writes Q into the workspace (fixed addresses, so captured
+        // cycle blocks stay valid for every chunk and call) and copies it out
+        double *qf = W.qf, *qc = W.qc;
+        TRY(launch_fill_i32(W.cycles, 0, 2 * int64_t(S), st));
+        TRY(launch_fill_u8(W.flags, 0, S, st));
+        TRY(launch_fill_f64(qc, 0.0, S, st));
+        KLArgs a{};
+        a.n = n;
+        a.M = M;
+        a.xi = x;
+        a.phi = ctx->d_phi[level];
+        a.ma = ctx->d_ma;
+        a.mb = ctx->d_mb;
+        a.sqrtlam = ctx->d_sqrtlam;
+        a.nlev = t + 1;
+        for (int j = 0; j <= t; ++j) {
+            const int k = t - j;  // pyramid slot j = grid index t - j
+            a.K64[j] = W.K64[k];
+            a.K32[j] = ir ? W.K32[k] : nullptr;
+            if (ir && !(k == t || (level >= 1 && k == t - 1))) a.K64[j] = nullptr;
+        }
+        W.top_grid = t;
+        const double klf = 2.0 * double(M) * double(n) * n * S;
+        TRY(timed(ctx, W, FMGMC_PROF_KL, klf, st, [&] { return launch_kl(a, S, ctx->opts.kl_prec, st); }));
+        TRY(ir ? run_batch_ir(ctx, W, tn, level, S, qf, qc, st) : run_batch_fp64(ctx, W, tn, level, S, qf, qc, st));
+        FMGMC_HIP(hipMemcpyAsync(q_fine + s0, qf, S * sizeof(double),
+                                 qf_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+        FMGMC_HIP(hipMemcpyAsync(q_coarse + s0, qc, S * sizeof(double),
+                                 qc_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+        if (cycles)
+            FMGMC_HIP(hipMemcpyAsync(cycles + 2 * s0, W.cycles, 2 * size_t(S) * sizeof(int32_t),
+                                     cy_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+        if (flags && fl_dev) FMGMC_HIP(hipMemcpyAsync(flags + s0, W.flags, S, hipMemcpyDeviceToDevice, st));
+        hflags.resize(S);
+        FMGMC_HIP(hipMemcpyAsync(hflags.data(), W.flags, S, hipMemcpyDeviceToHost, st));
+        FMGMC_HIP(hipStreamSynchronize(st));
+        if (flags && !fl_dev) std::memcpy(flags + s0, hflags.data(), S);
+        for (int s = 0; s < S; ++s) {
+            *any_notconv |= (hflags[s] & FMGMC_FLAG_NOTCONV) != 0;
+            *any_nonfinite |= (hflags[s] & FMGMC_FLAG_NONFINITE) != 0;
+        }
+    }
+    return FMGMC_OK;
+}
+
+int status_of(bool notconv, bool nonfinite, const char *who) {
+    if (nonfinite) {
+        set_error(std::string(who) + ": non-finite residual in some samples (see flags)");
+        return FMGMC_ENONFINITE;
+    }
+    if (notconv) {
+        set_error(std::string(who) + ": some samples did not reach rel_tol (see flags)");
+        return FMGMC_ENOTCONV;
+    }
+    return FMGMC_OK;
+}
+
+// Per-level workspace for fmgmc_solve_levels / fmgmc_autotune (created on first
+// use): the finest-level workspace's memory budget, at most 16384 samples.
+int level_work(fmgmc_ctx *c, int level, Work **out) {
+    if (!c->lev[level]) {
+        std::unique_ptr<Work> w(new Work());
+        const int n = c->hier.n0 << level;
+        const double scale = std::pow(double(c->hier.n0 << (c->hier.n_levels - 1)) / n, 2.0);
+        const int S = int(std::min<double>(16384.0, std::max<double>(c->main.S_max, c->main.S_max * scale)));
+        int rc = alloc_work(c, *w, S, n);
+        if (rc == FMGMC_OK && hipStreamCreateWithFlags(&w->own_stream, hipStreamNonBlocking) != hipSuccess) {
+            set_error("hipStreamCreate failed");
+            rc = FMGMC_EHIP;
+        }
+        if (rc != FMGMC_OK) {
+            free_work(*w);
+            return rc;
+        }
+        c->lev[level] = std::move(w);
+    }
+    *out = c->lev[level].get();
+    return FMGMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *fmgmc_last_error(void) { return g_err.c_str(); }
 
-int fmgmc_version(void) { return 100; }
+int fmgmc_version(void) { return 10100; }
 
 int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hier, const fmgmc_opts *opts,
                  int device) {
@@ -510,23 +712,24 @@ int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hi
     c->opts = *opts;
     c->device = device;
     if (c->opts.inner_cycles < 1) c->opts.inner_cycles = 1;
-    c->S_max = opts->max_batch > 0 ? opts->max_batch : 1024;
     int rc = build_mode_table(field->sigma2, field->corr_len, field->n_modes, c->table);
     if (rc != FMGMC_OK) {
         set_error("fmgmc_create: mode table");
         return rc;
     }
     const int nf = hier->n0 << (hier->n_levels - 1);
-    c->ng = ilog2(nf / hier->n_coarsest) + 1;
-    if (c->ng > kMaxGrid) {
+    if (ilog2(nf / hier->n_coarsest) + 1 > kMaxGrid) {
         set_error("fmgmc_create: too many grid levels");
         return FMGMC_EINVAL;
     }
-    for (int k = 0; k < c->ng; ++k) c->nsz[k] = hier->n_coarsest << k;
     c->small_top = ilog2(kSmallTop / hier->n_coarsest);
-    rc = allocate(c.get());
+    c->lev.resize(hier->n_levels);
+    c->tune.assign(hier->n_levels, Tune());
+    c->main.profile = true;
+    rc = alloc_constants(c.get());
+    if (rc == FMGMC_OK) rc = alloc_work(c.get(), c->main, opts->max_batch > 0 ? opts->max_batch : 1024, nf);
     if (rc != FMGMC_OK) {
-        free_all(c.get());
+        free_ctx(c.get());
         return rc;
     }
     *out = c.release();
@@ -565,7 +768,8 @@ int fmgmc_profile_read(fmgmc_ctx *ctx, int32_t kind, double *ms, int64_t *launch
     int rc = FMGMC_OK;
     for (auto &r : ctx->prof_rec[kind]) {
         float t = 0.f;
-        if (rc == FMGMC_OK && (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)) {
+        if (rc == FMGMC_OK &&
+            (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)) {
             set_error("fmgmc_profile_read: event error");
             rc = FMGMC_EHIP;
         }
@@ -589,7 +793,7 @@ int fmgmc_destroy(fmgmc_ctx *ctx) {
         int64_t n;
         fmgmc_profile_read(ctx, k, nullptr, &n, nullptr);
     }
-    free_all(ctx);
+    free_ctx(ctx);
     delete ctx;
     return FMGMC_OK;
 }
@@ -608,7 +812,8 @@ int fmgmc_mode_table(const fmgmc_ctx *ctx, int32_t *a, int32_t *b, double *lambd
     return m;
 }
 
-int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi, double *k_out, void *stream) {
+int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi, double *k_out,
+                           void *stream) {
     if (!ctx || level < 0 || level >= ctx->hier.n_levels || n_samples < 0 || (n_samples > 0 && (!xi || !k_out))) {
         set_error("fmgmc_synthesize_field: bad arguments");
         return FMGMC_EINVAL;
@@ -618,18 +823,19 @@ int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, con
     const int n = ctx->hier.n0 << level, M = ctx->table.M;
     const bool xi_dev = is_device_ptr(xi), k_dev = is_device_ptr(k_out);
     double *tmp = nullptr;
-    const int chunk = ctx->S_max;
+    const int chunk = ctx->main.S_max;
     if (!k_dev) TRY(dalloc(&tmp, size_t(chunk) * n * n));
     int rc = FMGMC_OK;
     for (int64_t s0 = 0; s0 < n_samples && rc == FMGMC_OK; s0 += chunk) {
         const int S = int(std::min<int64_t>(chunk, n_samples - s0));
         const double *x = xi + size_t(s0) * M;
         if (!xi_dev) {
-            if (hipMemcpyAsync(ctx->xi, x, size_t(S) * M * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) {
+            if (hipMemcpyAsync(ctx->main.xi, x, size_t(S) * M * sizeof(double), hipMemcpyHostToDevice, st) !=
+                hipSuccess) {
                 rc = FMGMC_EHIP;
                 break;
             }
-            x = ctx->xi;
+            x = ctx->main.xi;
         }
         KLArgs a{};
         a.n = n;
@@ -663,71 +869,131 @@ int fmgmc_solve_level(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const do
         return FMGMC_EINVAL;
     }
     DevGuard g(ctx->device);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int M = ctx->table.M;
-    const int n = ctx->hier.n0 << level;
-    const int t = ilog2(n / ctx->nsz[0]);
-    const bool ir = ir_mode(ctx);
-    const bool xi_dev = is_device_ptr(xi), qf_dev = is_device_ptr(q_fine), qc_dev = is_device_ptr(q_coarse);
-    const bool cy_dev = cycles && is_device_ptr(cycles), fl_dev = flags && is_device_ptr(flags);
-    bool any_notconv = false, any_nonfinite = false;
-    std::vector<uint8_t> hflags;
-    for (int64_t s0 = 0; s0 < n_samples; s0 += ctx->S_max) {
-        const int S = int(std::min<int64_t>(ctx->S_max, n_samples - s0));
-        const double *x = xi + size_t(s0) * M;
-        if (!xi_dev) {
-            FMGMC_HIP(hipMemcpyAsync(ctx->xi, x, size_t(S) * M * sizeof(double), hipMemcpyHostToDevice, st));
-            x = ctx->xi;
+    bool nc = false, nf = false;
+    TRY(solve_level_on(ctx, ctx->main, ctx->tune[level], level, n_samples, xi, q_fine, q_coarse, cycles, flags,
+                       reinterpret_cast<hipStream_t>(stream), &nc, &nf));
+    return status_of(nc, nf, "fmgmc_solve_level");
+}
+
+int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples, const double *const *xi,
+                       double *const *q_fine, double *const *q_coarse, int32_t *const *cycles,
+                       uint8_t *const *flags, void *stream) {
+    if (!ctx || n_lev < 1 || n_lev > ctx->hier.n_levels || !n_samples || !xi || !q_fine || !q_coarse) {
+        set_error("fmgmc_solve_levels: bad arguments");
+        return FMGMC_EINVAL;
+    }
+    for (int l = 0; l < n_lev; ++l)
+        if (n_samples[l] < 0 || (n_samples[l] > 0 && (!xi[l] || !q_fine[l] || !q_coarse[l]))) {
+            set_error("fmgmc_solve_levels: bad level arguments");
+            return FMGMC_EINVAL;
         }
-        double *qf = qf_dev ? q_fine + s0 : ctx->qf;
-        double *qc = qc_dev ? q_coarse + s0 : ctx->qc;
-        TRY(launch_fill_i32(ctx->cycles, 0, 2 * int64_t(S), st));
-        TRY(launch_fill_u8(ctx->flags, 0, S, st));
-        TRY(launch_fill_f64(qc, 0.0, S, st));
-        KLArgs a{};
-        a.n = n;
-        a.M = M;
-        a.xi = x;
-        a.phi = ctx->d_phi[level];
-        a.ma = ctx->d_ma;
-        a.mb = ctx->d_mb;
-        a.sqrtlam = ctx->d_sqrtlam;
-        a.nlev = t + 1;
-        for (int j = 0; j <= t; ++j) {
-            const int k = t - j;  // pyramid slot j = grid index t - j
-            a.K64[j] = ctx->K64[k];
-            a.K32[j] = ir ? ctx->K32[k] : nullptr;
-            if (ir && !(k == t || (level >= 1 && k == t - 1))) a.K64[j] = nullptr;
+    DevGuard g(ctx->device);
+    // the levels' inputs may have been produced on the caller's stream
+    FMGMC_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+    std::vector<Work *> ws(n_lev, nullptr);
+    for (int l = 0; l < n_lev; ++l)
+        if (n_samples[l] > 0) TRY(level_work(ctx, l, &ws[l]));
+    std::vector<int> rcs(n_lev, FMGMC_OK);
+    std::vector<std::string> msgs(n_lev);
+    std::vector<char> ncs(n_lev, 0), nfs(n_lev, 0);
+    auto run = [&](int l) {
+        (void)hipSetDevice(ctx->device);
+        bool nc = false, nf = false;
+        rcs[l] = solve_level_on(ctx, *ws[l], ctx->tune[l], l, n_samples[l], xi[l], q_fine[l], q_coarse[l],
+                                cycles ? cycles[l] : nullptr, flags ? flags[l] : nullptr, ws[l]->own_stream, &nc,
+                                &nf);
+        if (rcs[l] != FMGMC_OK) msgs[l] = g_err;
+        ncs[l] = nc;
+        nfs[l] = nf;
+    };
+    // the finest level on the calling thread, every other level on a thread of its own
+    std::vector<std::thread> th;
+    for (int l = 0; l < n_lev - 1; ++l)
+        if (n_samples[l] > 0) th.emplace_back(run, l);
+    if (n_samples[n_lev - 1] > 0) run(n_lev - 1);
+    for (auto &t : th) t.join();
+    bool nc = false, nf = false;
+    for (int l = 0; l < n_lev; ++l) {
+        if (rcs[l] != FMGMC_OK) {
+            set_error("fmgmc_solve_levels: level " + std::to_string(l) + ": " + msgs[l]);
+            return rcs[l];
         }
-        ctx->top_grid = t;
-        const double klf = 2.0 * double(M) * double(n) * n * S;
-        TRY(timed(ctx, FMGMC_PROF_KL, klf, st, [&] { return launch_kl(a, S, ctx->opts.kl_prec, st); }));
-        TRY(ir ? run_batch_ir(ctx, level, S, qf, qc, st) : run_batch_fp64(ctx, level, S, qf, qc, st));
-        // outputs
-        if (!qf_dev) FMGMC_HIP(hipMemcpyAsync(q_fine + s0, qf, S * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (!qc_dev) FMGMC_HIP(hipMemcpyAsync(q_coarse + s0, qc, S * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (cycles)
-            FMGMC_HIP(hipMemcpyAsync(cycles + 2 * s0, ctx->cycles, 2 * size_t(S) * sizeof(int32_t),
-                                     cy_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-        if (flags && fl_dev)
-            FMGMC_HIP(hipMemcpyAsync(flags + s0, ctx->flags, S, hipMemcpyDeviceToDevice, st));
-        hflags.resize(S);
-        FMGMC_HIP(hipMemcpyAsync(hflags.data(), ctx->flags, S, hipMemcpyDeviceToHost, st));
-        FMGMC_HIP(hipStreamSynchronize(st));
-        if (flags && !fl_dev) std::memcpy(flags + s0, hflags.data(), S);
-        for (int s = 0; s < S; ++s) {
-            any_notconv |= (hflags[s] & FMGMC_FLAG_NOTCONV) != 0;
-            any_nonfinite |= (hflags[s] & FMGMC_FLAG_NONFINITE) != 0;
+        nc |= ncs[l] != 0;
+        nf |= nfs[l] != 0;
+    }
+    return status_of(nc, nf, "fmgmc_solve_levels");
+}
+
+int fmgmc_autotune(fmgmc_ctx *ctx, int32_t level, int64_t n_pilot, const double *xi, int32_t *params) {
+    if (!ctx || level < 0 || level >= ctx->hier.n_levels || n_pilot < 1 || !xi) {
+        set_error("fmgmc_autotune: bad arguments");
+        return FMGMC_EINVAL;
+    }
+    DevGuard g(ctx->device);
+    Work *W = nullptr;
+    TRY(level_work(ctx, level, &W));
+    const int64_t np = std::min<int64_t>(n_pilot, W->S_max);
+    double *qf = nullptr, *qc = nullptr, *dxi = nullptr;
+    int rc = dalloc(&qf, np);
+    if (rc == FMGMC_OK) rc = dalloc(&qc, np);
+    if (rc == FMGMC_OK) rc = dalloc(&dxi, size_t(np) * ctx->table.M);
+    if (rc == FMGMC_OK &&
+        hipMemcpy(dxi, xi, size_t(np) * ctx->table.M * sizeof(double), hipMemcpyDefault) != hipSuccess) {
+        set_error("fmgmc_autotune: copy failed");
+        rc = FMGMC_EHIP;
+    }
+    Tune best = ctx->tune[level];
+    double best_ms = 1e300;
+    const bool saved_prof = ctx->prof;
+    ctx->prof = false;
+    const int batches[3] = {W->S_max, std::max(1, W->S_max / 2), std::max(1, W->S_max / 4)};
+    for (int G : {1, 2, 4, 8}) {
+        for (int graphs : {0, 1}) {
+            for (int bi = 0; bi < 3 && rc == FMGMC_OK; ++bi) {
+                if (bi > 0 && batches[bi] >= np) continue;
+                Tune tn;
+                tn.check_every = G;
+                tn.graphs = graphs;
+                tn.batch = batches[bi];
+                double ms = 1e300;
+                for (int rep = 0; rep < 2 && rc == FMGMC_OK; ++rep) {  // first run warms graphs and caches
+                    bool nc = false, nf = false;
+                    const auto t0 = std::chrono::steady_clock::now();
+                    rc = solve_level_on(ctx, *W, tn, level, np, dxi, qf, qc, nullptr, nullptr, W->own_stream, &nc,
+                                        &nf);
+                    const auto t1 = std::chrono::steady_clock::now();
+                    ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+                }
+                if (rc == FMGMC_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = tn;
+                }
+            }
         }
     }
-    if (any_nonfinite) {
-        set_error("fmgmc_solve_level: non-finite residual in some samples (see flags)");
-        return FMGMC_ENONFINITE;
+    ctx->prof = saved_prof;
+    dfree(qf);
+    dfree(qc);
+    dfree(dxi);
+    if (rc != FMGMC_OK) return rc;
+    ctx->tune[level] = best;
+    if (params) {
+        params[0] = best.check_every;
+        params[1] = best.graphs;
+        params[2] = best.batch;
     }
-    if (any_notconv) {
-        set_error("fmgmc_solve_level: some samples did not reach rel_tol (see flags)");
-        return FMGMC_ENOTCONV;
+    return FMGMC_OK;
+}
+
+int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params) {
+    if (!ctx || level < 0 || level >= ctx->hier.n_levels || !params || params[0] < 1 || params[1] < 0 ||
+        params[1] > 1 || params[2] < 0) {
+        set_error("fmgmc_set_schedule: bad arguments");
+        return FMGMC_EINVAL;
     }
+    ctx->tune[level].check_every = params[0];
+    ctx->tune[level].graphs = params[1];
+    ctx->tune[level].batch = params[2];
     return FMGMC_OK;
 }
 
@@ -757,7 +1023,10 @@ int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf, con
             f = tf;
         }
         if (!is_device_ptr(cc)) {
-            if ((rc = dalloc(&tc, n[l])) != FMGMC_OK) { dfree(tf); break; }
+            if ((rc = dalloc(&tc, n[l])) != FMGMC_OK) {
+                dfree(tf);
+                break;
+            }
             (void)hipMemcpyAsync(tc, cc, n[l] * sizeof(double), hipMemcpyHostToDevice, st);
             cc = tc;
         }
@@ -781,8 +1050,7 @@ int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf, con
             levels[l].var_qf = h[3];
             levels[l].mean_qc = h[4];
         }
-        // Neumaier over the (few) levels
-        const double tt = total + h[0];
+        const double tt = total + h[0];  // Neumaier over the (few) levels
         totc += (std::fabs(total) >= std::fabs(h[0])) ? (total - tt) + h[0] : (h[0] - tt) + total;
         total = tt;
         var += (n_shifts > 1) ? h[1] : h[1] / double(n[l]);

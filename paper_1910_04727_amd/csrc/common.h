@@ -109,8 +109,8 @@ struct KLArgs {
     const int32_t *ma, *mb;
     const double *sqrtlam;// [M]
     int nlev;             // pyramid levels written (finest first): n, n/2, ...
-    double *K64[8];       // nullable per level
-    float *K32[8];        // nullable per level
+    double *K64[9];       // nullable per level
+    float *K32[9];        // nullable per level
 };
 int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st);
 

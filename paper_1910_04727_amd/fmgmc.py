@@ -57,6 +57,9 @@ _SIGS = {
     "fmgmc_synthesize_field": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP]),
     "fmgmc_solve_level": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fmgmc_estimate": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "fmgmc_solve_levels": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "fmgmc_autotune": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP]),
+    "fmgmc_set_schedule": (C.c_int, [_VP, C.c_int32, _VP]),
     "fmgmc_profile_enable": (C.c_int, [_VP, C.c_int32]),
     "fmgmc_profile_read": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
     "fmgmc_last_error": (C.c_char_p, []),
@@ -192,6 +195,29 @@ class Context:
         rc = lib().fmgmc_solve_level(self._h, level, ns, _ptr(xi), _ptr(q_fine), _ptr(q_coarse),
                                      _ptr(cycles), _ptr(flags), _stream_ptr(stream))
         return _check(rc, allow)
+
+
+    def solve_levels(self, xis, q_fines, q_coarses, cycles=None, flags=None, stream=None,
+                     allow=(ENOTCONV, ENONFINITE)):
+        """All levels at once (level l gets xis[l], ...); returns the status code."""
+        L = len(xis)
+        ns = np.array([int(x.shape[0]) for x in xis], np.int64)
+        tabs = [(C.c_void_p * L)(*[_ptr(x) for x in xs]) if xs is not None else None
+                for xs in (xis, q_fines, q_coarses, cycles, flags)]
+        rc = lib().fmgmc_solve_levels(self._h, L, _ptr(ns),
+                                      *[C.addressof(t) if t is not None else None for t in tabs],
+                                      _stream_ptr(stream))
+        return _check(rc, allow)
+
+    def autotune(self, level, xi_pilot):
+        """Measured schedule (check interval, graphs, batch) for a level."""
+        p = np.zeros(3, np.int32)
+        _check(lib().fmgmc_autotune(self._h, level, xi_pilot.shape[0], _ptr(xi_pilot), _ptr(p)))
+        return dict(check_every=int(p[0]), graphs=int(p[1]), batch=int(p[2]))
+
+    def set_schedule(self, level, check_every=1, graphs=0, batch=0):
+        p = np.array([check_every, graphs, batch], np.int32)
+        _check(lib().fmgmc_set_schedule(self._h, level, _ptr(p)))
 
 
 def _check_count(rc):

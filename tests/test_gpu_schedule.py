@@ -1,0 +1,157 @@
+"""Schedules never change results: all levels at once, graph replay, batch size.
+
+Every sample runs the same kernels in the same order whatever the schedule
+(cycles per host check, HIP-graph replay of the cycle blocks, samples per
+device chunk, one stream per MLMC level), so results must agree bit for bit
+with the plain eager per-level solve. The eager per-level solve is itself
+parity-tested against the oracle in test_gpu_parity.py; here one small case is
+also checked against the oracle directly.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_1910_04727_amd import fmgmc, inputs
+
+pytestmark = pytest.mark.gpu
+
+CFG1 = dict(sigma2=1.0, corr_len=0.3, n_modes=64, n_levels=3, n0=16)
+CFG2 = dict(sigma2=1.0, corr_len=0.2, n_modes=256, n_levels=5, n0=32)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fmgmc.lib()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def bufs(S):
+    return (torch.zeros(S, dtype=torch.float64, device="cuda"),
+            torch.zeros(S, dtype=torch.float64, device="cuda"),
+            torch.zeros((S, 2), dtype=torch.int32, device="cuda"),
+            torch.zeros(S, dtype=torch.uint8, device="cuda"))
+
+
+def solve(ctx, level, xi_dev):
+    qf, qc, cyc, fl = bufs(xi_dev.shape[0])
+    rc = ctx.solve_level(level, xi_dev, qf, qc, cyc, fl)
+    torch.cuda.synchronize()
+    return rc, qf.cpu().numpy(), qc.cpu().numpy(), cyc.cpu().numpy(), fl.cpu().numpy()
+
+
+def same(a, b, label):
+    for name, x, y in zip(("rc", "qf", "qc", "cycles", "flags"), a, b):
+        assert np.array_equal(np.asarray(x), np.asarray(y)), f"{label}: {name} differs"
+
+
+@pytest.mark.parametrize("solver", ["fp64", "fp32_ir"])
+def test_solve_levels_equals_per_level(solver):
+    """All three levels of the 16/32/64 hierarchy at once, ragged sample counts."""
+    ns = [37, 21, 13]
+    xis = [torch.from_numpy(inputs.mc_normals(ns[l], CFG1["n_modes"], config=1, level=l)).to("cuda")
+           for l in range(3)]
+    log(f"solve_levels {solver} ns {ns}")
+    with fmgmc.Context(**CFG1, solver=solver, max_batch=16) as ctx:
+        ref = [solve(ctx, l, xis[l]) for l in range(3)]
+        outs = [bufs(n) for n in ns]
+        rc = ctx.solve_levels(xis, [o[0] for o in outs], [o[1] for o in outs],
+                              [o[2] for o in outs], [o[3] for o in outs])
+        torch.cuda.synchronize()
+        for l in range(3):
+            assert ref[l][0] == 0
+            same((0,) + tuple(t.cpu().numpy() for t in outs[l]), ref[l], f"level {l}")
+        assert rc == 0
+        # a second call reuses the per-level workspaces and streams
+        outs2 = [bufs(n) for n in ns]
+        ctx.solve_levels(xis, [o[0] for o in outs2], [o[1] for o in outs2])
+        torch.cuda.synchronize()
+        for l in range(3):
+            assert np.array_equal(outs2[l][0].cpu().numpy(), ref[l][1])
+            assert np.array_equal(outs2[l][1].cpu().numpy(), ref[l][2])
+
+
+def test_solve_levels_host_buffers_and_oracle():
+    """Host inputs and outputs; level 1 (32^2, coarse stage 16^2) against the oracle."""
+    ns = [0, 6, 5]
+    xis = [inputs.mc_normals(max(n, 1), CFG1["n_modes"], config=1, level=l)[:n] for l, n in enumerate(ns)]
+    qf = [np.zeros(n) for n in ns]
+    qc = [np.zeros(n) for n in ns]
+    with fmgmc.Context(**CFG1, solver="fp64") as ctx:
+        rc = ctx.solve_levels(xis, qf, qc)
+    assert rc == 0
+    tab = O.kl_table(CFG1["sigma2"], CFG1["corr_len"], CFG1["n_modes"])
+    of, oc, _, _ = O.solve_level(CFG1["sigma2"], CFG1["corr_len"], tab, 32, 1, xis[1])
+    np.testing.assert_allclose(qf[1], of, rtol=1e-9)
+    np.testing.assert_allclose(qc[1], oc, rtol=1e-9)
+
+
+@pytest.mark.parametrize("solver,level", [("fp64", 1), ("fp32_ir", 1), ("fp64", 3), ("fp32_ir", 3)])
+def test_graph_replay_matches_eager(solver, level):
+    """Graph-replayed cycle blocks on 64^2 (LDS kernel) and 256^2 (marching kernels).
+
+    Several calls replay the captured blocks, with unrelated eager GPU work and
+    synchronisations between them; every replay must equal the eager result.
+    The batch (5) is below the sample count (13), so chunks replay the graphs
+    too, the last one with its own (ragged) batch size.
+    """
+    S = 13
+    xi = torch.from_numpy(inputs.mc_normals(S, CFG2["n_modes"], config=2, level=level, purpose=3)).to("cuda")
+    with fmgmc.Context(**CFG2, solver=solver, max_batch=8) as ctx:
+        ctx.set_schedule(level, check_every=1, graphs=0, batch=5)
+        eager = solve(ctx, level, xi)
+        log(f"graph {solver} level {level}: eager cycles max {eager[3].max(axis=0)}")
+        for G in (1, 3):
+            ctx.set_schedule(level, check_every=G, graphs=1, batch=5)
+            for rep in range(3):
+                junk = torch.randn(1 << 20, device="cuda")
+                junk.mul_(2.0).sum().item()
+                torch.cuda.synchronize()
+                same(solve(ctx, level, xi), eager, f"G={G} replay {rep}")
+        # the same context back on the eager schedule and the full batch
+        ctx.set_schedule(level, check_every=2, graphs=0, batch=0)
+        same(solve(ctx, level, xi), eager, "eager G=2 full batch")
+
+
+def test_graph_replay_on_user_stream():
+    """Per-level solve on a caller's non-default stream with graphs on."""
+    level, S = 2, 9
+    xi = torch.from_numpy(inputs.mc_normals(S, CFG2["n_modes"], config=2, level=level, purpose=3)).to("cuda")
+    with fmgmc.Context(**CFG2, solver="fp32_ir") as ctx:
+        eager = solve(ctx, level, xi)
+        ctx.set_schedule(level, check_every=2, graphs=1, batch=0)
+        s = torch.cuda.Stream()
+        for rep in range(3):
+            qf, qc, cyc, fl = bufs(S)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                rc = ctx.solve_level(level, xi, qf, qc, cyc, fl, stream=s)
+            s.synchronize()
+            same((rc, qf.cpu().numpy(), qc.cpu().numpy(), cyc.cpu().numpy(), fl.cpu().numpy()), eager,
+                 f"stream replay {rep}")
+
+
+def test_autotune_picks_valid_schedule_and_keeps_results():
+    level, S = 2, 24
+    xi = torch.from_numpy(inputs.mc_normals(S, CFG2["n_modes"], config=2, level=level, purpose=4)).to("cuda")
+    with fmgmc.Context(**CFG2, solver="fp32_ir", max_batch=16) as ctx:
+        before = solve(ctx, level, xi)
+        p = ctx.autotune(level, xi)
+        log(f"autotune level {level}: {p}")
+        assert p["check_every"] in (1, 2, 4, 8) and p["graphs"] in (0, 1) and p["batch"] >= 1
+        same(solve(ctx, level, xi), before, "after autotune")
+
+
+def test_schedule_argument_errors():
+    with fmgmc.Context(**CFG1) as ctx:
+        for bad in ((0, 0, 0), (1, 2, 0), (1, 0, -1)):
+            with pytest.raises(RuntimeError):
+                ctx.set_schedule(0, *bad)
+        with pytest.raises(RuntimeError):
+            ctx.set_schedule(3, 1, 0, 0)
