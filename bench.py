@@ -110,8 +110,278 @@ def cpu_baseline(xi, n_samples):
                       f"{dt:.1f} s wall on {threads} threads"}
 
 
+# ----------------------------------------------------------------- reports
+# Each report workload runs one configuration end to end on the GPU and
+# prints one JSON line: correctness against the oracle on a subset, the
+# estimator, and throughput. They are not the headline measurement.
+
+def _t(torch):
+    torch.cuda.synchronize()
+    return time.perf_counter()
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _bufs(torch, S):
+    return (torch.zeros(S, dtype=torch.float64, device="cuda"), torch.zeros(S, dtype=torch.float64, device="cuda"),
+            torch.zeros((S, 2), dtype=torch.int32, device="cuda"), torch.zeros(S, dtype=torch.uint8, device="cuda"))
+
+
+def _rel(a, b):
+    r = np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300)
+    return dict(max=float(r.max()), median=float(np.median(r))) if r.size else None
+
+
+def _oracle_subset(cfg, level, xi, tol):
+    from oracle import oracle as O
+    tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
+    qf, qc, cyc, fl = O.solve_level(cfg["sigma2"], cfg["corr_len"], tab, cfg["n0"] << level, level, xi, tol=tol,
+                                    nthreads=O.max_threads())
+    return qf, qc
+
+
+def report_cfg1(torch, fmgmc, inputs, args):
+    """3 levels (16^2, 32^2, 64^2), 1000 samples each, FP64, every sample against the oracle."""
+    from oracle import oracle as O
+    cfg = dict(sigma2=1.0, corr_len=0.3, n_modes=64, n_levels=3, n0=16)
+    ns = [1000, 1000, 1000]
+    xis = [inputs.mc_normals(n, cfg["n_modes"], config=1, level=l) for l, n in enumerate(ns)]
+    xd = [_dev(torch, x) for x in xis]
+    out = [_bufs(torch, n) for n in ns]
+    with fmgmc.Context(**cfg, solver="fp64") as ctx:
+        ctx.solve_levels(xd, [o[0] for o in out], [o[1] for o in out])
+        t0 = _t(torch)
+        for _ in range(args.steps):
+            rc = ctx.solve_levels(xd, [o[0] for o in out], [o[1] for o in out], [o[2] for o in out],
+                                  [o[3] for o in out])
+        dt = (_t(torch) - t0) / args.steps
+    est = fmgmc.estimate([o[0] for o in out], [o[1] for o in out])
+    tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
+    lv, oq = [], []
+    for l in range(3):
+        of, oc, ocyc, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], tab, cfg["n0"] << l, l, xis[l],
+                                        nthreads=O.max_threads())
+        oq.append((of, oc))
+        g = out[l][0].cpu().numpy()
+        gc = out[l][1].cpu().numpy()
+        same = np.all(out[l][2].cpu().numpy() == ocyc, axis=1)
+        lv.append(dict(n=cfg["n0"] << l, samples=ns[l], qf_rel_err=_rel(g, of),
+                       qc_rel_err=_rel(gc[oc != 0], oc[oc != 0]) if l else None,
+                       same_cycle_counts=float(same.mean()), flags=int(out[l][3].cpu().numpy().sum())))
+    ost = [O.level_stats(of, oc) for of, oc in oq]
+    omean = sum(s["mean_y"] for s in ost)
+    return {"metric": "cfg1 FP64 FMG-MLMC, all samples against the oracle", "value": round(sum(ns) / dt, 1),
+            "unit": "samples/s", "status": int(rc), "levels": lv, "estimate": est["mean"], "oracle_estimate": omean,
+            "estimate_rel_diff": abs(est["mean"] - omean) / abs(omean), "var_of_mean": est["var_of_mean"],
+            "config": {"workload": "3 levels 16^2/32^2/64^2, sigma2=1, corr_len=0.3, 64 KL modes, 1000 samples "
+                                   "per level, FP64 FMG to rel-res 1e-10, all levels in one solve_levels call"}}
+
+
+def _cfg2_counts():
+    with open(os.path.join(ROOT, "tests", "golden", "cfg2_nl.json")) as f:
+        return json.load(f)["n_l"]
+
+
+def report_cfg2(torch, fmgmc, inputs, args):
+    """The 5-level estimate with the frozen per-level counts, FP64 and FP32+IR."""
+    cfg = dict(CFG)
+    ns = _cfg2_counts()
+    L = len(ns)
+    R = max(1, -(-ns[0] // (1 << 21)))  # rounds of at most 2M level-0 samples
+    Q = {f: [[np.empty(n), np.empty(n)] for n in ns] for f in ("fp64", "fp32_ir")}
+    cyc = {f: [np.empty((n, 2), np.int32) for n in ns] for f in Q}
+    tsolve = {f: 0.0 for f in Q}
+    tseq = 0.0
+    flags = {f: 0 for f in Q}
+    ctxs = {f: fmgmc.Context(**cfg, solver=f, max_batch=2048, max_cycles=60) for f in Q}
+    for r in range(R):
+        lo = [n * r // R for n in ns]
+        hi = [n * (r + 1) // R for n in ns]
+        xd = [_dev(torch, inputs.mc_normals_blocked(lo[l], hi[l] - lo[l], cfg["n_modes"], config=2, level=l))
+              for l in range(L)]
+        for f, ctx in ctxs.items():
+            out = [_bufs(torch, hi[l] - lo[l]) for l in range(L)]
+            if r == 0:  # untimed warm-up (workspaces, code objects)
+                ctx.solve_levels(xd, [o[0] for o in out], [o[1] for o in out])
+            t0 = _t(torch)
+            ctx.solve_levels(xd, [o[0] for o in out], [o[1] for o in out], [o[2] for o in out], [o[3] for o in out])
+            tsolve[f] += _t(torch) - t0
+            for l in range(L):
+                Q[f][l][0][lo[l]:hi[l]] = out[l][0].cpu().numpy()
+                Q[f][l][1][lo[l]:hi[l]] = out[l][1].cpu().numpy()
+                cyc[f][l][lo[l]:hi[l]] = out[l][2].cpu().numpy()
+                flags[f] += int((out[l][3].cpu().numpy() != 0).sum())
+            if f == "fp32_ir":  # the same round level by level, one after another
+                t0 = _t(torch)
+                for l in range(L):
+                    ctx.solve_level(l, xd[l], out[l][0], out[l][1])
+                tseq += _t(torch) - t0
+        log(f"cfg2 round {r + 1}/{R} done")
+        del xd
+    for c in ctxs.values():
+        c.close()
+    from oracle import oracle as O
+    res = {}
+    for f in Q:
+        est = fmgmc.estimate([q[0] for q in Q[f]], [q[1] for q in Q[f]])
+        ost = [O.level_stats(q[0], q[1]) for q in Q[f]]
+        res[f] = dict(samples_per_s=round(sum(ns) / tsolve[f], 1), seconds=round(tsolve[f], 3),
+                      estimate=est["mean"], var_of_mean=est["var_of_mean"],
+                      sampling_rmse=float(np.sqrt(est["var_of_mean"])),
+                      oracle_stats_of_same_q=sum(s["mean_y"] for s in ost), flagged=flags[f],
+                      cycles_mean=[[round(float(c[:, 0].mean()), 3), round(float(c[:, 1].mean()), 3)]
+                                   for c in cyc[f]],
+                      var_y=[float(s["var_y"]) for s in ost])
+    res["fp32_ir"]["sequential_levels_samples_per_s"] = round(sum(ns) / tseq, 1)
+    # per-sample QoI error against the oracle driven to 1e-12 (first 16 samples per level)
+    err = {f: [] for f in Q}
+    for l in range(L):
+        k = min(16, ns[l])
+        xi = inputs.mc_normals_blocked(0, k, cfg["n_modes"], config=2, level=l)
+        of, oc = _oracle_subset(cfg, l, xi, 1e-12)
+        for f in Q:
+            e = [np.abs(Q[f][l][0][:k] - of) / np.abs(of)]
+            if l:
+                e.append(np.abs(Q[f][l][1][:k] - oc) / np.abs(oc))
+            err[f].append(np.concatenate(e))
+    for f in Q:
+        e = np.concatenate(err[f])
+        res[f]["qoi_rel_err_vs_oracle_1e-12"] = dict(max=float(e.max()), median=float(np.median(e)),
+                                                     samples=int(e.size))
+    res["estimate_rel_diff_fp32_ir_vs_fp64"] = abs(res["fp32_ir"]["estimate"] - res["fp64"]["estimate"]) / abs(
+        res["fp64"]["estimate"])
+    return {"metric": "cfg2 5-level FMG-MLMC estimate", "value": res["fp32_ir"]["samples_per_s"],
+            "unit": "samples/s", "n_l": ns, "forms": res,
+            "config": {"workload": "5 levels 32^2..512^2, sigma2=1, corr_len=0.2, 256 KL modes, frozen N_l "
+                                   "(pilot + optimal allocation for RMSE 1e-3, scaled to 4096 on 512^2), "
+                                   "rel-res 1e-10, all levels per solve_levels call, blocked PCG64 inputs"}}
+
+
+def report_cfg3(torch, fmgmc, inputs, args):
+    """RQMC (Sobol' 2^14 x 16 shifts) against MC (2^18 i.i.d.) per level; KL in FP64 / FP32 / BF16."""
+    cfg = dict(sigma2=2.0, corr_len=0.1, n_modes=512, n_levels=4, n0=64)
+    m_log2, R = 14, 16
+    N = R << m_log2
+    forms = {"kl_fp64": "fp64", "kl_fp32": "fp32", "kl_bf16": "bf16"}
+    ctxs = {k: fmgmc.Context(**cfg, solver="fp32_ir", kl_prec=p, max_batch=2048, max_cycles=60)
+            for k, p in forms.items()}
+    lv = []
+    tot = dict(var_rqmc=0.0, var_mc=0.0, est_rqmc=0.0, est_mc=0.0, seconds=0.0)
+    kl_est = {k: 0.0 for k in forms}
+    for l in range(cfg["n_levels"]):
+        xq_host = inputs.rqmc_normals(cfg["n_modes"], m_log2, R, config=3, level=l)
+        xq = _dev(torch, xq_host)
+        row = dict(n=cfg["n0"] << l)
+        q = {}
+        for k, ctx in ctxs.items():
+            qf, qc, c, fl = _bufs(torch, N)
+            t0 = _t(torch)
+            ctx.solve_level(l, xq, qf, qc, c, fl)
+            dt = _t(torch) - t0
+            q[k] = (qf, qc)
+            e = fmgmc.estimate([qf], [qc], n_shifts=R)
+            kl_est[k] += e["mean"]
+            if k == "kl_fp64":
+                row.update(rqmc_mean=e["mean"], rqmc_var_of_mean=e["var_of_mean"], seconds=dt,
+                           cycles_mean=[round(float(x), 3) for x in c.double().mean(0).cpu().numpy()],
+                           flagged=int((fl != 0).sum().item()))
+                tot["est_rqmc"] += e["mean"]
+                tot["var_rqmc"] += e["var_of_mean"]
+                tot["seconds"] += dt
+        for k in ("kl_fp32", "kl_bf16"):
+            a = torch.cat(q[k]).cpu().numpy()
+            b = torch.cat(q["kl_fp64"]).cpu().numpy()
+            m = b != 0
+            row[f"{k}_qoi_rel_err"] = _rel(a[m], b[m])
+        del xq, q
+        xm = _dev(torch, inputs.mc_normals_blocked(0, N, cfg["n_modes"], config=3, level=l))
+        qf, qc, c, fl = _bufs(torch, N)
+        ctxs["kl_fp64"].solve_level(l, xm, qf, qc, c, fl)
+        e = fmgmc.estimate([qf], [qc])
+        row.update(mc_mean=e["mean"], mc_var_of_mean=e["var_of_mean"],
+                   variance_ratio_mc_over_rqmc=e["var_of_mean"] / row["rqmc_var_of_mean"])
+        tot["est_mc"] += e["mean"]
+        tot["var_mc"] += e["var_of_mean"]
+        # oracle check of the FP64-KL path on the first 4 RQMC points
+        xo = np.ascontiguousarray(xq_host[:4])
+        del xq_host
+        of, oc = _oracle_subset(cfg, l, xo, 1e-12)
+        qf4, qc4, _, _ = _bufs(torch, 4)
+        ctxs["kl_fp64"].solve_level(l, _dev(torch, xo), qf4, qc4)
+        row["fp64_kl_qoi_rel_err_vs_oracle_1e-12"] = _rel(qf4.cpu().numpy(), of)
+        lv.append(row)
+        log(f"cfg3 level {l} done")
+        del xm
+    for c in ctxs.values():
+        c.close()
+    return {"metric": "cfg3 MLQMC vs MLMC estimator variance at equal cost", "value":
+            round(tot["var_mc"] / tot["var_rqmc"], 3), "unit": "variance ratio MC/RQMC (total)",
+            "levels": lv, "total": tot, "kl_precision_estimates": kl_est,
+            "config": {"workload": "4 levels 64^2..512^2, sigma2=2, corr_len=0.1, 512 KL modes, 2^14 Sobol' "
+                                   "points x 16 digital shifts per level vs 2^18 i.i.d.; FP32+IR to 1e-10; "
+                                   "KL contraction in FP64, FP32 and BF16"}}
+
+
+def report_cfg4(torch, fmgmc, inputs, args):
+    """6 levels 32^2..1024^2 at once (65536 samples), FP32+IR: sequential vs concurrent vs autotuned."""
+    cfg = dict(sigma2=3.0, corr_len=0.05, n_modes=1024, n_levels=6, n0=32)
+    ns = [42451, 15007, 5306, 1875, 663, 234]
+    L = len(ns)
+    xd = [_dev(torch, inputs.mc_normals_blocked(0, n, cfg["n_modes"], config=4, level=l)) for l, n in enumerate(ns)]
+    out = [_bufs(torch, n) for n in ns]
+    res = {}
+    with fmgmc.Context(**cfg, solver="fp32_ir", max_batch=512, max_cycles=60) as ctx:
+        def seq():
+            for l in range(L):
+                ctx.solve_level(l, xd[l], out[l][0], out[l][1], out[l][2], out[l][3])
+
+        def conc():
+            return ctx.solve_levels(xd, [o[0] for o in out], [o[1] for o in out], [o[2] for o in out],
+                                    [o[3] for o in out])
+        for name, fn in (("sequential_levels", seq), ("concurrent_levels", conc)):
+            fn()
+            t0 = _t(torch)
+            fn()
+            res[name] = round(sum(ns) / (_t(torch) - t0), 1)
+            log(f"cfg4 {name}: {res[name]} samples/s")
+        ref = [(o[0].cpu().numpy().copy(), o[1].cpu().numpy().copy()) for o in out]
+        t0 = time.perf_counter()
+        sched = [ctx.autotune(l, xd[l][:2048]) for l in range(L)]
+        res["autotune_seconds"] = round(time.perf_counter() - t0, 2)
+        conc()
+        t0 = _t(torch)
+        rc = conc()
+        res["concurrent_autotuned"] = round(sum(ns) / (_t(torch) - t0), 1)
+        same = all(np.array_equal(o[0].cpu().numpy(), r[0]) and np.array_equal(o[1].cpu().numpy(), r[1])
+                   for o, r in zip(out, ref))
+    lv = []
+    for l in range(L):
+        c = out[l][2].cpu().numpy()
+        lv.append(dict(n=cfg["n0"] << l, samples=ns[l], schedule=sched[l],
+                       cycles_mean=[round(float(x), 3) for x in c.mean(0)], cycles_max=[int(x) for x in c.max(0)],
+                       flagged=int((out[l][3].cpu().numpy() != 0).sum())))
+    k = 4
+    xo = xd[L - 1][:k].cpu().numpy()
+    of, oc = _oracle_subset(cfg, L - 1, xo, 1e-10)
+    est = fmgmc.estimate([o[0] for o in out], [o[1] for o in out])
+    return {"metric": "cfg4 uneven-size batched stress", "value": res["concurrent_autotuned"], "unit": "samples/s",
+            "status": int(rc), "throughput": res, "autotuned_results_identical": bool(same), "levels": lv,
+            "estimate": est["mean"], "var_of_mean": est["var_of_mean"],
+            "qf_1024_rel_err_vs_oracle": _rel(out[L - 1][0][:k].cpu().numpy(), of),
+            "qc_1024_rel_err_vs_oracle": _rel(out[L - 1][1][:k].cpu().numpy(), oc),
+            "config": {"workload": "6 levels 32^2..1024^2, sigma2=3, corr_len=0.05, 1024 KL modes, N_l = "
+                                   f"{ns} (65536 total), FP32+IR to rel-res 1e-10, batch 512"}}
+
+
+REPORTS = {"cfg1": report_cfg1, "cfg2": report_cfg2, "cfg3": report_cfg3, "cfg4": report_cfg4}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="headline", choices=["headline"] + sorted(REPORTS),
+                    help="headline (default): the 512^2 samples/s line; others print one report line each")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -136,6 +406,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload != "headline":
+        out = REPORTS[args.workload](torch, fmgmc, inputs, args)
+        print(json.dumps(out), flush=True)
+        return
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -7,6 +7,10 @@ oracle consume, so that every form sees bit-identical inputs.
   - Monte Carlo (Section 2.1, Eq. (3)): i.i.d. N(0,1) from numpy's PCG64,
     seeded by SeedSequence([seed, config, level, purpose]); levels use
     independent streams, as the estimator requires (Eq. (5)).
+  - Large Monte Carlo runs (millions of samples on a level) use a blocked
+    variant: sample s of a level is row s % B of block s // B, each block an
+    independent PCG64 stream seeded by SeedSequence([seed, config, level,
+    purpose, block]), so blocks can be drawn in parallel and in any order.
   - Randomised QMC (Section 2.4): a scrambled Sobol' point set (scipy's
     Owen-type scrambling), then R random digital shifts (XOR of 30-bit
     integers), mapped through the inverse normal CDF at the dyadic cell
@@ -36,6 +40,37 @@ def mc_normals(n, M, config, level, purpose=PURPOSE_ESTIMATOR, seed=SEED, offset
     if offset:
         g.standard_normal((offset, M))
     return g.standard_normal((n, M))
+
+
+MC_BLOCK = 65536
+
+
+def _block_rows(config, level, purpose, seed, M, b, r0, r1):
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, config, level, purpose, b])))
+    if r0:
+        g.standard_normal((r0, M))
+    return g.standard_normal((r1 - r0, M))
+
+
+def mc_normals_blocked(start, n, M, config, level, purpose=PURPOSE_ESTIMATOR, seed=SEED, threads=16):
+    """Rows [start, start + n) of the blocked stream, [n, M] float64."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty((n, M))
+    jobs = []
+    s = start
+    while s < start + n:
+        b, r0 = divmod(s, MC_BLOCK)
+        r1 = min(MC_BLOCK, r0 + (start + n - s))
+        jobs.append((s - start, b, r0, r1))
+        s += r1 - r0
+
+    def run(j):
+        o, b, r0, r1 = j
+        out[o:o + r1 - r0] = _block_rows(config, level, purpose, seed, M, b, r0, r1)
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        list(ex.map(run, jobs))
+    return out
 
 
 def sobol_ints(M, m_log2, config, level, seed=SEED):

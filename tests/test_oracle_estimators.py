@@ -74,6 +74,19 @@ def test_inputs_are_reproducible_and_independent_per_level():
     assert np.array_equal(tail, inputs.mc_normals(8, 16, config=2, level=3)[3:])
 
 
+def test_blocked_stream_is_position_independent():
+    """Any window of the blocked stream equals the same rows of a larger draw;
+    blocks are distinct streams; levels and purposes differ."""
+    B = inputs.MC_BLOCK
+    full = inputs.mc_normals_blocked(B - 3, 10, 4, config=2, level=0, threads=3)
+    assert np.array_equal(full[:3], inputs.mc_normals_blocked(B - 3, 3, 4, config=2, level=0))
+    assert np.array_equal(full[3:], inputs.mc_normals_blocked(B, 7, 4, config=2, level=0))
+    assert not np.array_equal(full[3:5], inputs.mc_normals_blocked(0, 2, 4, config=2, level=0))
+    assert not np.array_equal(full, inputs.mc_normals_blocked(B - 3, 10, 4, config=2, level=1))
+    z = inputs.mc_normals_blocked(0, 4096, 8, config=2, level=0)
+    assert abs(z.mean()) < 4 * (1 / np.sqrt(z.size)) and abs(z.var() - 1) < 0.05
+
+
 def test_sobol_points_are_a_digital_net():
     """Every 1-D projection of the first 2^k scrambled Sobol' points puts exactly one
     point in each dyadic interval of width 2^-k; an XOR digital shift keeps that."""
