@@ -57,6 +57,10 @@ def lib():
             "oracle_level_stats": (_i, [_i64, _pd, _pd, _pd]),
             "oracle_rqmc_stats": (_i, [_i64, _i, _pd, _pd, _pd, C.c_void_p]),
             "oracle_optimal_nl": (None, [_i, _pd, _pd, _d, _pl]),
+            "oracle_cnn_nparams": (_i64, [_i, _i, _i]),
+            "oracle_cnn_forward": (None, [_i, _i, _i, _i, _i, _pd, _pd, _pd, C.c_void_p, C.c_void_p]),
+            "oracle_cnn_loss_grad": (_d, [_i, _i, _i, _i, _i, _pd, _pd, _pd, _pd]),
+            "oracle_adam": (None, [_i64, _pd, _pd, _pd, _pd, _i, _d, _d, _d, _d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -258,3 +262,36 @@ def optimal_nl(V, Cst, eps):
     N = np.zeros(len(V), np.int64)
     lib().oracle_optimal_nl(len(V), V, Cst, eps, N)
     return N
+
+
+# --- learned warm start (oracle/cnn.c) ------------------------------------
+CNN_CIN, CNN_WIDTH, CNN_RES = 2, 32, 4
+
+
+def cnn_nparams(cin=CNN_CIN, F=CNN_WIDTH, R=CNN_RES):
+    return int(lib().oracle_cnn_nparams(cin, F, R))
+
+
+def cnn_forward(theta, x, cin=CNN_CIN, F=CNN_WIDTH, R=CNN_RES, acts=False):
+    """x [B][cin][n][n] -> y [B][n][n] (and z, h [B][R+1][F][n][n] if acts)."""
+    x = _f64(x)
+    B, n = x.shape[0], x.shape[-1]
+    y = np.zeros((B, n, n))
+    z = np.zeros((B, R + 1, F, n, n)) if acts else None
+    h = np.zeros((B, R + 1, F, n, n)) if acts else None
+    lib().oracle_cnn_forward(n, B, cin, F, R, _f64(theta), x, y,
+                             z.ctypes.data if acts else None, h.ctypes.data if acts else None)
+    return (y, z, h) if acts else y
+
+
+def cnn_loss_grad(theta, x, t, cin=CNN_CIN, F=CNN_WIDTH, R=CNN_RES):
+    x = _f64(x)
+    B, n = x.shape[0], x.shape[-1]
+    g = np.zeros(cnn_nparams(cin, F, R))
+    L = lib().oracle_cnn_loss_grad(n, B, cin, F, R, _f64(theta), x, _f64(t), g)
+    return L, g
+
+
+def adam(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place on theta, m, v (float64 arrays)."""
+    lib().oracle_adam(theta.size, theta, _f64(g), m, v, t, lr, beta1, beta2, eps)
