@@ -17,7 +17,13 @@
  *   y  = conv(hR, Wo) + bo                                      (F -> 1)
  * Parameters, flattened in this order: W0 [F][C_in][3][3], b0 [F], then for
  * k = 1..R: Wk [F][F][3][3], bk [F], then Wo [1][F][3][3], bo [1].
- * Loss over a batch of B samples: L = (1 / (B n^2)) sum (y - t)^2.
+ * Losses over a batch of B samples:
+ *   error loss     L = (1 / (B n^2)) sum (y - t)^2 for targets t;
+ *   residual loss  L = (1 / (B n^2)) sum (x1 - A y)^2, where A is the stage
+ *     operator of Section 3.1 (1) (harmonic faces, 2K on the Dirichlet faces,
+ *     homogeneous boundary data) built from K = exp(x0). With x1 = r / rms(r)
+ *     and the start p~ + rms(r) y, x1 - A y is the normalised residual of the
+ *     corrected start, the quantity the FMG stopping rule measures.
  * Optimiser: Adam (Kingma and Ba, 2015) with bias correction.
  */
 #include <math.h>
@@ -118,10 +124,15 @@ void oracle_cnn_forward(int n, int B, int cin, int F, int R, const double *theta
     free(hh);
 }
 
+/* FV operator of oracle.c (pinned by its closed forms) */
+void oracle_faces(int n, const double *K, double *Tx, double *Ty);
+void oracle_apply(int n, const double *Tx, const double *Ty, const double *x, double *y);
+
 /* Loss and its gradient with respect to the parameters (grad, same layout as
- * theta) for targets t [B][n][n]. Returns L. */
-double oracle_cnn_loss_grad(int n, int B, int cin, int F, int R, const double *theta, const double *x,
-                            const double *t, double *grad)
+ * theta): kind 0 = error loss with targets t [B][n][n], kind 1 = residual loss
+ * (t unused). Returns L. */
+double oracle_cnn_loss_grad_kind(int n, int B, int cin, int F, int R, const double *theta, const double *x,
+                                 const double *t, int kind, double *grad)
 {
     const size_t N = (size_t)n * n;
     const int64_t np = oracle_cnn_nparams(cin, F, R);
@@ -131,6 +142,8 @@ double oracle_cnn_loss_grad(int n, int B, int cin, int F, int R, const double *t
     double *gh = malloc(sizeof(double) * F * N);
     double *gz = malloc(sizeof(double) * F * N);
     double *gy = malloc(sizeof(double) * N);
+    double *K = malloc(sizeof(double) * N), *Tx = malloc(sizeof(double) * n * (n + 1));
+    double *Ty = malloc(sizeof(double) * n * (n + 1)), *u = malloc(sizeof(double) * N);
     memset(grad, 0, sizeof(double) * np);
     double L = 0.0;
     const double inv = 1.0 / ((double)B * (double)N);
@@ -138,10 +151,24 @@ double oracle_cnn_loss_grad(int n, int B, int cin, int F, int R, const double *t
     const int64_t o_out = (int64_t)F * cin * 9 + F + (int64_t)R * (F * F * 9 + F);
     for (int s = 0; s < B; ++s) {
         oracle_cnn_forward(n, 1, cin, F, R, theta, x + (size_t)s * cin * N, y, z, h);
-        for (size_t k = 0; k < N; ++k) {
-            const double d = y[k] - t[(size_t)s * N + k];
-            L += d * d * inv;
-            gy[k] = 2.0 * d * inv;
+        if (kind == 0) {
+            for (size_t k = 0; k < N; ++k) {
+                const double d = y[k] - t[(size_t)s * N + k];
+                L += d * d * inv;
+                gy[k] = 2.0 * d * inv;
+            }
+        } else {
+            /* u = x1 - A y; dL/dy = -2 A^T u / (B n^2), and A is symmetric */
+            const double *x0 = x + (size_t)s * cin * N, *x1 = x0 + N;
+            for (size_t k = 0; k < N; ++k) K[k] = exp(x0[k]);
+            oracle_faces(n, K, Tx, Ty);
+            oracle_apply(n, Tx, Ty, y, u);
+            for (size_t k = 0; k < N; ++k) {
+                u[k] = x1[k] - u[k];
+                L += u[k] * u[k] * inv;
+            }
+            oracle_apply(n, Tx, Ty, u, gy);
+            for (size_t k = 0; k < N; ++k) gy[k] *= -2.0 * inv;
         }
         /* output layer */
         conv3_w(n, F, 1, gy, h + (size_t)R * F * N, grad + o_out, grad + o_out + F * 9);
@@ -164,7 +191,17 @@ double oracle_cnn_loss_grad(int n, int B, int cin, int F, int R, const double *t
     free(gh);
     free(gz);
     free(gy);
+    free(K);
+    free(Tx);
+    free(Ty);
+    free(u);
     return L;
+}
+
+double oracle_cnn_loss_grad(int n, int B, int cin, int F, int R, const double *theta, const double *x,
+                            const double *t, double *grad)
+{
+    return oracle_cnn_loss_grad_kind(n, B, cin, F, R, theta, x, t, 0, grad);
 }
 
 /* One Adam step (step count t >= 1 after this update) on np parameters. */

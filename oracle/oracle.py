@@ -60,6 +60,7 @@ def lib():
             "oracle_cnn_nparams": (_i64, [_i, _i, _i]),
             "oracle_cnn_forward": (None, [_i, _i, _i, _i, _i, _pd, _pd, _pd, C.c_void_p, C.c_void_p]),
             "oracle_cnn_loss_grad": (_d, [_i, _i, _i, _i, _i, _pd, _pd, _pd, _pd]),
+            "oracle_cnn_loss_grad_kind": (_d, [_i, _i, _i, _i, _i, _pd, _pd, C.c_void_p, _i, _pd]),
             "oracle_adam": (None, [_i64, _pd, _pd, _pd, _pd, _i, _d, _d, _d, _d]),
         }
         for name, (res, args) in sig.items():
@@ -289,6 +290,15 @@ def cnn_loss_grad(theta, x, t, cin=CNN_CIN, F=CNN_WIDTH, R=CNN_RES):
     B, n = x.shape[0], x.shape[-1]
     g = np.zeros(cnn_nparams(cin, F, R))
     L = lib().oracle_cnn_loss_grad(n, B, cin, F, R, _f64(theta), x, _f64(t), g)
+    return L, g
+
+
+def cnn_residual_loss_grad(theta, x, cin=CNN_CIN, F=CNN_WIDTH, R=CNN_RES):
+    """Residual loss mean((x1 - A y)^2), A from K = exp(x0); returns (L, grad)."""
+    x = _f64(x)
+    B, n = x.shape[0], x.shape[-1]
+    g = np.zeros(cnn_nparams(cin, F, R))
+    L = lib().oracle_cnn_loss_grad_kind(n, B, cin, F, R, _f64(theta), x, None, 1, g)
     return L, g
 
 

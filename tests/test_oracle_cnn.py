@@ -107,3 +107,62 @@ def test_adam_first_step_closed_form():
     th2 = th1.copy()
     O.adam(th2, g, m, v, 2, 1e-3)
     np.testing.assert_allclose(th2, th1 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
+
+
+def test_residual_loss_gradient_matches_central_differences():
+    cin, F, R, n, B = 2, 3, 1, 6, 2
+    rng = np.random.default_rng(13)
+    th = rand_net(rng, cin, F, R)
+    x = rng.standard_normal((B, cin, n, n))
+    L, g = O.cnn_residual_loss_grad(th, x, cin, F, R)
+    h = 1e-6
+    for k in range(th.size):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (O.cnn_residual_loss_grad(tp, x, cin, F, R)[0] - O.cnn_residual_loss_grad(tm, x, cin, F, R)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-7 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
+def test_residual_loss_against_torch_with_an_independent_operator():
+    """The residual loss rebuilt in torch: the FV operator from padded harmonic
+    means (Dirichlet faces 2K, no-flow north/south), the network from conv2d."""
+    torch = pytest.importorskip("torch")
+    import torch.nn.functional as Fn
+    cin, F, R, n, B = O.CNN_CIN, O.CNN_WIDTH, O.CNN_RES, 6, 2
+    rng = np.random.default_rng(17)
+    th = rand_net(rng, cin, F, R, 0.1)
+    x = rng.standard_normal((B, cin, n, n))
+    L_o, g_o = O.cnn_residual_loss_grad(th, x, cin, F, R)
+    tt = torch.tensor(th, requires_grad=True)
+    p, off = [], 0
+    for ws, bs in [((F, cin, 3, 3), F)] + [((F, F, 3, 3), F)] * R + [((1, F, 3, 3), 1)]:
+        nw = int(np.prod(ws))
+        p.append((tt[off:off + nw].view(ws), tt[off + nw:off + nw + bs]))
+        off += nw + bs
+    a = torch.tensor(x)
+    hcur = torch.relu(Fn.conv2d(a, p[0][0], p[0][1], padding=1))
+    for k in range(1, R + 1):
+        hcur = hcur + torch.relu(Fn.conv2d(hcur, p[k][0], p[k][1], padding=1))
+    y = Fn.conv2d(hcur, p[-1][0], p[-1][1], padding=1)[:, 0]
+    K = torch.exp(a[:, 0])
+    hm = lambda u, v: 2 * u * v / (u + v)
+    Tx = torch.cat([2 * K[:, :, :1], hm(K[:, :, :-1], K[:, :, 1:]), 2 * K[:, :, -1:]], dim=2)  # [B][n][n+1]
+    z = torch.zeros_like(K[:, :1, :])
+    Ty = torch.cat([z, hm(K[:, :-1, :], K[:, 1:, :]), z], dim=1)                          # [B][n+1][n]
+    yp = Fn.pad(y, (1, 1, 1, 1))
+    Ay = ((Tx[:, :, :-1] + Tx[:, :, 1:] + Ty[:, :-1, :] + Ty[:, 1:, :]) * y
+          - Tx[:, :, :-1] * yp[:, 1:-1, :-2] - Tx[:, :, 1:] * yp[:, 1:-1, 2:]
+          - Ty[:, :-1, :] * yp[:, :-2, 1:-1] - Ty[:, 1:, :] * yp[:, 2:, 1:-1])
+    L = ((a[:, 1] - Ay) ** 2).mean()
+    L.backward()
+    assert abs(L.item() - L_o) <= 1e-13 * L_o
+    gt = tt.grad.numpy()
+    assert np.max(np.abs(gt - g_o)) <= 1e-12 * np.abs(gt).max()
+
+
+def test_residual_loss_of_the_zero_network_is_the_mean_square_residual():
+    rng = np.random.default_rng(19)
+    x = rng.standard_normal((2, 2, 5, 5))
+    L, _ = O.cnn_residual_loss_grad(np.zeros(O.cnn_nparams()), x)
+    assert abs(L - np.mean(x[:, 1] ** 2)) <= 1e-15
