@@ -52,7 +52,8 @@ enum {
 /* per-sample flag bits */
 enum {
     FMGMC_FLAG_NOTCONV = 1,    /* a QoI stage stopped at max_cycles above rel_tol */
-    FMGMC_FLAG_NONFINITE = 2   /* non-finite residual or coefficient */
+    FMGMC_FLAG_NONFINITE = 2,  /* non-finite residual or coefficient */
+    FMGMC_FLAG_WARM_REJECTED = 4  /* the learned start was worse than the FMG start and was discarded */
 };
 
 enum { FMGMC_COV_SEPARABLE_EXP = 0 };
@@ -213,15 +214,100 @@ int fmgmc_kl_modes(double sigma2, double corr_len, int32_t n_modes, int32_t *a, 
  * KL contraction) is accumulated from the number of samples still iterating.
  * Kinds: 0 pre-smoothing + residual + restriction pass, 1 prolongation +
  * post-smoothing pass (+ residual norm, QoI), 2 FP64 refinement pass,
- * 3 KL synthesis, 4 coarse-grid V-cycle in LDS.
+ * 3 KL synthesis, 4 coarse-grid V-cycle in LDS, 5 warm-start network
+ * inference (flops; all its layers, every QoI stage it runs on).
  * fmgmc_profile_read synchronises, returns the summed kernel time in ms,
  * the launch count and the algorithmic bytes (flops for kind 3), and clears
  * the kind's record.
  */
 enum { FMGMC_PROF_PRE = 0, FMGMC_PROF_POST = 1, FMGMC_PROF_IR = 2, FMGMC_PROF_KL = 3,
-       FMGMC_PROF_SMALL = 4, FMGMC_PROF_KINDS = 5 };
+       FMGMC_PROF_SMALL = 4, FMGMC_PROF_CNN = 5, FMGMC_PROF_KINDS = 6 };
 int fmgmc_profile_enable(fmgmc_ctx *ctx, int32_t enable);
 int fmgmc_profile_read(fmgmc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *alg);
+
+/*
+ * ---------------------------------------------------------------------------
+ * Learned warm start of the FMG pass. The paper has no network: its FMG pass
+ * (Section 2.5) starts each stage from the bilinear interpolation p~ of the
+ * stage below. A small residual convolutional network proposes a correction
+ * of that start on a QoI stage grid; the stage then iterates to rel_tol as
+ * before, so every Q still meets the same stopping rule, and the plain start
+ * is kept whenever the proposal does not lower ||b - A p||_2 (flag bit
+ * FMGMC_FLAG_WARM_REJECTED).
+ *
+ * Network (fixed shape, FMGMC_CNN_PARAMS parameters): 3x3 zero-padded
+ * cross-correlations, input x = (log K, r / rms(r)) with r = b - A p~ and
+ * rms(r) = ||r||_2 / n; h0 = relu(conv(x) + b0) with 32 channels; four
+ * residual layers h_k = h_{k-1} + relu(conv(h_{k-1}) + b_k); output
+ * y = conv(h_4) + b_5 (1 channel); the start becomes p~ + rms(r) y.
+ * Parameters are FP32, flattened per layer as W[c_out][c_in][3][3] then
+ * b[c_out], layers in order. Training: FP32 forward/backward and Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on one of two losses over a batch of B
+ * samples: the residual loss (1 / (B n^2)) sum (x1 - A y)^2, A the stage
+ * operator built from K = exp(x0), i.e. the normalised residual of the
+ * corrected start (what the stopping rule measures; the training loop uses
+ * it), or the error loss (1 / (B n^2)) sum (y - t)^2 against targets t.
+ * Inference in the solver: BF16 on the matrix cores with FP32 accumulation.
+ * ---------------------------------------------------------------------------
+ */
+#define FMGMC_CNN_PARAMS 37889
+enum { FMGMC_CNN_FP32 = 0, FMGMC_CNN_BF16 = 1 };
+enum { FMGMC_CNN_LOSS_ERROR = 0, FMGMC_CNN_LOSS_RESIDUAL = 1 };
+typedef struct fmgmc_cnn fmgmc_cnn;
+
+/* New network on `device`: He-normal weights from `seed` (deterministic), zero biases. */
+int fmgmc_cnn_create(fmgmc_cnn **out, uint64_t seed, int32_t device);
+int fmgmc_cnn_destroy(fmgmc_cnn *cnn);
+/* Parameter copy out / in (FMGMC_CNN_PARAMS floats, host or device). set resets Adam. */
+int fmgmc_cnn_get_params(const fmgmc_cnn *cnn, float *theta);
+int fmgmc_cnn_set_params(fmgmc_cnn *cnn, const float *theta);
+/* Flat file: 8-byte tag "FMGCNN01", int32 {2, 32, 4, 0}, then the FP32 parameters. */
+int fmgmc_cnn_save(const fmgmc_cnn *cnn, const char *path);
+int fmgmc_cnn_load(fmgmc_cnn *cnn, const char *path);
+
+/*
+ * Forward pass on device buffers: x [batch][2][n][n] float (channel 0 = log K,
+ * channel 1 = the normalised residual), y [batch][n][n] float. n a power of
+ * two in [16, 1024]. prec FMGMC_CNN_FP32 (training kernels) or
+ * FMGMC_CNN_BF16 (the solver's inference kernels).
+ */
+int fmgmc_cnn_forward(fmgmc_cnn *cnn, int32_t n, int64_t batch, const float *x, float *y, int32_t prec,
+                      void *stream);
+/*
+ * Loss (loss_kind FMGMC_CNN_LOSS_RESIDUAL, t may be NULL; or
+ * FMGMC_CNN_LOSS_ERROR with targets t [batch][n][n], device) into *loss (host)
+ * and, if grad is non-NULL, the gradient (FMGMC_CNN_PARAMS floats, host or
+ * device). The gradient is also kept for fmgmc_cnn_adam, which applies one
+ * Adam step.
+ */
+int fmgmc_cnn_grad(fmgmc_cnn *cnn, int32_t n, int64_t batch, const float *x, const float *t, int32_t loss_kind,
+                   double *loss, float *grad, void *stream);
+int fmgmc_cnn_adam(fmgmc_cnn *cnn, double lr, void *stream);
+
+/*
+ * Training pairs generated by the method itself: solves n_samples samples of
+ * `level` (FP32_IR solver) and, on each QoI stage, writes the network input
+ * x at the FMG start and the target t = (p - p~) / rms(r), p the converged
+ * stage solution. Coarse-stage buffers ([n][2][n_l/2]^2 and [n][n_l/2]^2) are
+ * written for level >= 1 only (nullable); fine-stage ones ([n][2][n_l]^2,
+ * [n][n_l]^2) always. Outputs are device buffers; xi host or device.
+ */
+int fmgmc_cnn_make_data(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi, float *x_coarse,
+                        float *t_coarse, float *x_fine, float *t_fine, void *stream);
+/*
+ * Trains on inputs from `level` with the residual loss: for each batch of
+ * `batch` samples of xi, one Adam step on the fine-stage inputs, then
+ * (level >= 1, n_l/2 >= 16) one on the coarse-stage inputs. loss_hist
+ * (nullable, host) receives the losses in that order.
+ */
+int fmgmc_cnn_train(fmgmc_ctx *ctx, fmgmc_cnn *cnn, int32_t level, int64_t n_samples, const double *xi,
+                    int32_t batch, double lr, double *loss_hist);
+/*
+ * Uses `cnn` (NULL: off) to warm-start every QoI stage with n >= min_n in the
+ * FP32_IR solver. The context keeps the pointer; the caller keeps the
+ * network alive and does not train it while the context solves.
+ */
+int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n);
 
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *fmgmc_last_error(void);

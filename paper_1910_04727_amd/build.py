@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmgmc.so")
-SOURCES = ["api.cpp", "kl_table.cpp", "kl.hip", "march.hip", "small.hip", "misc.hip"]
+SOURCES = ["api.cpp", "kl_table.cpp", "cnn.cpp", "kl.hip", "march.hip", "small.hip", "misc.hip",
+           "cnn_train.hip", "cnn_infer.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-Wno-unused-result"]

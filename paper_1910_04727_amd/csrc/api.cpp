@@ -35,6 +35,7 @@
 #include <tuple>
 #include <vector>
 
+#include "cnn.h"
 #include "common.h"
 
 namespace fmgmc {
@@ -119,6 +120,15 @@ struct Work {
     int top_grid = -1;
     bool profile = false;           // profiling records allowed for this workspace
     hipStream_t own_stream = nullptr;
+    // learned warm start: inference activations (bf16, act_cap bytes each), residual
+    // norms at the FMG start, and for training pairs the FMG start itself
+    void *act[2] = {};
+    size_t act_cap = 0;
+    double *rr0 = nullptr;
+    double *p0 = nullptr;
+    size_t p0_cap = 0;
+    float *capx_base[2] = {}, *capt_base[2] = {};  // training-pair outputs (slot 0 coarse, 1 fine)
+    float *cap_x[2] = {}, *cap_t[2] = {};          // the current chunk's views
     // captured cycle blocks, keyed by (MLMC level, stage grid, block length, batch size)
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
 };
@@ -134,6 +144,12 @@ void free_work(Work &w) {
     }
     dfree(w.chol); dfree(w.rr); dfree(w.q); dfree(w.bnorm); dfree(w.qf); dfree(w.qc); dfree(w.xi);
     dfree(w.active); dfree(w.cycles); dfree(w.n_active); dfree(w.flags);
+    for (int k = 0; k < 2; ++k)
+        if (w.act[k]) (void)hipFree(w.act[k]);
+    w.act[0] = w.act[1] = nullptr;
+    w.act_cap = 0;
+    dfree(w.rr0); dfree(w.p0);
+    w.p0_cap = 0;
     if (w.h_n_active) (void)hipHostFree(w.h_n_active);
     w.h_n_active = nullptr;
     for (auto &kv : w.graphs) (void)hipGraphExecDestroy(kv.second);
@@ -161,6 +177,8 @@ struct fmgmc_ctx {
     Work main;                                  // finest-level workspace (fmgmc_solve_level)
     std::vector<std::unique_ptr<Work>> lev;     // per-level workspaces (fmgmc_solve_levels)
     std::vector<Tune> tune;                     // per MLMC level
+    const fmgmc_cnn *warm = nullptr;            // learned warm start (not owned)
+    int warm_min_n = 256;
     // measurement hooks
     struct Rec {
         hipEvent_t a, b;
@@ -219,6 +237,7 @@ int alloc_work(const fmgmc_ctx *c, Work &w, int S, int n_top) {
     TRY(dalloc(&w.qf, S)); TRY(dalloc(&w.qc, S)); TRY(dalloc(&w.xi, size_t(S) * M));
     TRY(dalloc(&w.active, S)); TRY(dalloc(&w.cycles, 2 * size_t(S))); TRY(dalloc(&w.n_active, 1));
     TRY(dalloc(&w.flags, S));
+    TRY(dalloc(&w.rr0, S));
     if (hipHostMalloc(reinterpret_cast<void **>(&w.h_n_active), sizeof(int32_t)) != hipSuccess) {
         set_error("hipHostMalloc failed");
         return FMGMC_ENOMEM;
@@ -491,6 +510,46 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
     return FMGMC_OK;
 }
 
+// Learned warm start of one QoI stage (p64 holds the FMG start p~, rr its
+// residual norm, r32 its residual): p~ + rms(r) y, then the plain start is
+// restored for every sample whose residual did not drop.
+template <typename F>
+int warm_start(fmgmc_ctx *c, Work &W, int k, int S, const IRArgs &ia, hipStream_t st, F &&interp) {
+    const int n = W.nsz[k];
+    const size_t per = size_t(n) * n * kCnnWidth * 2;
+    const int sub = int(std::max<size_t>(1, std::min<size_t>(size_t(S), (size_t(256) << 20) / per)));
+    if (W.act_cap < sub * per) {
+        FMGMC_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < 2; ++j) {
+            if (W.act[j]) (void)hipFree(W.act[j]);
+            W.act[j] = nullptr;
+        }
+        W.act_cap = 0;
+        for (int j = 0; j < 2; ++j) TRY(dalloc(reinterpret_cast<char **>(&W.act[j]), sub * per));
+        W.act_cap = sub * per;
+    }
+    InferArgs a{};
+    a.n = n;
+    a.S = S;
+    a.in0 = W.K32[k];
+    a.in1 = W.b32[k];
+    a.in_stride = int64_t(n) * n;
+    a.log0 = 1;
+    a.rr = W.rr0;
+    a.p = W.p64[k];
+    a.active = W.active;
+    // useful flops per cell, 2 per multiply-add: first layer 18 x 32, four residual
+    // layers 288 x 32 each, output layer 288
+    const double flops = double(W.n_active_host) * n * n * 2.0 * (18.0 * 32 + 4.0 * 288 * 32 + 288);
+    TRY(timed(c, W, FMGMC_PROF_CNN, flops, st,
+              [&] { return launch_cnn_infer(a, cnn_packed(c->warm), W.act[0], W.act[1], sub, st); }));
+    TRY(launch_ir(ia, S, st));
+    TRY(launch_judge(S, W.rr, W.rr0, W.active, W.flags, st));  // active <- samples to restore
+    TRY(interp());
+    TRY(launch_ir(ia, S, st));
+    return launch_fill_i32(W.active, 1, S, st);
+}
+
 int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double *qf, double *qc,
                  hipStream_t st) {
     const int t = ilog2((c->hier.n0 << level) / W.nsz[0]);
@@ -511,10 +570,11 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
         const int slot = fine ? 1 : 0;
         const int n = W.nsz[k];
         // FMG start in FP64
-        if (fine && level >= 1)
-            TRY(launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, pW, pE, S, st));
-        else
-            TRY(launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, pW, pE, S, st));
+        auto interp = [&]() -> int {
+            if (fine && level >= 1) return launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, pW, pE, S, st);
+            return launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, pW, pE, S, st);
+        };
+        TRY(interp());
         TRY(launch_bnorm<double>(n, W.K64[k], pW, pE, W.bnorm, S, st));
         IRArgs ia{};
         ia.n = n;
@@ -533,6 +593,14 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
             else TRY(launch_ir(ia, S, st));
         }
+        const bool warm = c->warm && n >= c->warm_min_n;
+        float *capx = W.cap_x[slot], *capt = W.cap_t[slot];
+        if (warm || capx) TRY(launch_copy_f64(W.rr, W.rr0, S, st));
+        if (capx) {
+            TRY(launch_pack_x(n, S, W.K32[k], W.b32[k], W.rr0, capx, st));
+            TRY(launch_copy_f64(W.p64[k], W.p0, int64_t(S) * n * n, st));
+        }
+        if (warm) TRY(warm_start(c, W, k, S, ia, st, interp));
         const int inner = std::max(1, c->opts.inner_cycles);
         auto step = [&]() -> int {
             for (int ic = 0; ic < inner; ++ic)
@@ -548,6 +616,7 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
         TRY(step());
         TRY(read_active(W, st, &na));
         TRY(iterate_stage(c, W, tn, level, k, S, inner, na, st, step));
+        if (capt) TRY(launch_pack_t(n, S, W.p64[k], W.p0, W.rr0, capt, st));
     }
     return FMGMC_OK;
 }
@@ -622,6 +691,11 @@ int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n
             if (ir && !(k == t || (level >= 1 && k == t - 1))) a.K64[j] = nullptr;
         }
         W.top_grid = t;
+        for (int sl = 0; sl < 2; ++sl) {
+            const int ns = sl == 1 ? n : n / 2;
+            W.cap_x[sl] = W.capx_base[sl] ? W.capx_base[sl] + size_t(s0) * 2 * ns * ns : nullptr;
+            W.cap_t[sl] = W.capt_base[sl] ? W.capt_base[sl] + size_t(s0) * ns * ns : nullptr;
+        }
         const double klf = 2.0 * double(M) * double(n) * n * S;
         TRY(timed(ctx, W, FMGMC_PROF_KL, klf, st, [&] { return launch_kl(a, S, ctx->opts.kl_prec, st); }));
         TRY(ir ? run_batch_ir(ctx, W, tn, level, S, qf, qc, st) : run_batch_fp64(ctx, W, tn, level, S, qf, qc, st));
@@ -995,6 +1069,98 @@ int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params) {
     ctx->tune[level].graphs = params[1];
     ctx->tune[level].batch = params[2];
     return FMGMC_OK;
+}
+
+int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n) {
+    if (!ctx || min_n < 16 || (cnn && !ir_mode(ctx)) || (cnn && cnn->device != ctx->device)) {
+        set_error("fmgmc_set_warm_start: bad arguments (FP32_IR solver, min_n >= 16, same device)");
+        return FMGMC_EINVAL;
+    }
+    DevGuard g(ctx->device);
+    if (cnn) {
+        TRY(cnn_ensure_packed(const_cast<fmgmc_cnn *>(cnn), nullptr));
+        FMGMC_HIP(hipStreamSynchronize(nullptr));
+    }
+    ctx->warm = cnn;
+    ctx->warm_min_n = min_n;
+    return FMGMC_OK;
+}
+
+int fmgmc_cnn_make_data(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi, float *x_coarse,
+                        float *t_coarse, float *x_fine, float *t_fine, void *stream) {
+    if (!ctx || level < 0 || level >= ctx->hier.n_levels || n_samples < 1 || !xi || !x_fine || !t_fine ||
+        !ir_mode(ctx) || (!x_coarse) != (!t_coarse)) {
+        set_error("fmgmc_cnn_make_data: bad arguments (FP32_IR solver)");
+        return FMGMC_EINVAL;
+    }
+    const int n = ctx->hier.n0 << level;
+    if (n < 16 || (x_coarse && (level < 1 || n / 2 < 16))) {
+        set_error("fmgmc_cnn_make_data: stage grids must be at least 16 x 16");
+        return FMGMC_EINVAL;
+    }
+    DevGuard g(ctx->device);
+    Work &W = ctx->main;
+    const size_t need = size_t(W.S_max) * n * n;
+    if (W.p0_cap < need) {
+        dfree(W.p0);
+        W.p0_cap = 0;
+        TRY(dalloc(&W.p0, need));
+        W.p0_cap = need;
+    }
+    std::vector<double> qf(n_samples), qc(n_samples);
+    W.capx_base[1] = x_fine;
+    W.capt_base[1] = t_fine;
+    W.capx_base[0] = x_coarse;
+    W.capt_base[0] = t_coarse;
+    const fmgmc_cnn *warm = ctx->warm;
+    ctx->warm = nullptr;  // targets are relative to the plain FMG start
+    bool nc = false, nf = false;
+    const int rc = solve_level_on(ctx, W, ctx->tune[level], level, n_samples, xi, qf.data(), qc.data(), nullptr,
+                                  nullptr, reinterpret_cast<hipStream_t>(stream), &nc, &nf);
+    ctx->warm = warm;
+    for (int k = 0; k < 2; ++k) W.capx_base[k] = W.capt_base[k] = W.cap_x[k] = W.cap_t[k] = nullptr;
+    TRY(rc);
+    return status_of(nc, nf, "fmgmc_cnn_make_data");
+}
+
+int fmgmc_cnn_train(fmgmc_ctx *ctx, fmgmc_cnn *cnn, int32_t level, int64_t n_samples, const double *xi,
+                    int32_t batch, double lr, double *loss_hist) {
+    if (!ctx || !cnn || level < 0 || level >= ctx->hier.n_levels || n_samples < 1 || !xi || batch < 1 ||
+        !(lr > 0) || cnn->device != ctx->device) {
+        set_error("fmgmc_cnn_train: bad arguments");
+        return FMGMC_EINVAL;
+    }
+    DevGuard g(ctx->device);
+    const int n = ctx->hier.n0 << level, nc = n / 2, M = ctx->table.M;
+    const bool coarse = level >= 1 && nc >= 16;
+    const int B = int(std::min<int64_t>(batch, std::min<int64_t>(n_samples, ctx->main.S_max)));
+    float *xf = nullptr, *tf = nullptr, *xc = nullptr, *tc = nullptr;
+    int rc = dalloc(&xf, size_t(B) * 2 * n * n);
+    if (rc == FMGMC_OK) rc = dalloc(&tf, size_t(B) * n * n);
+    if (rc == FMGMC_OK && coarse) rc = dalloc(&xc, size_t(B) * 2 * nc * nc);
+    if (rc == FMGMC_OK && coarse) rc = dalloc(&tc, size_t(B) * nc * nc);
+    int64_t h = 0;
+    for (int64_t b0 = 0; b0 < n_samples && (rc == FMGMC_OK || rc == FMGMC_ENOTCONV); b0 += B) {
+        const int S = int(std::min<int64_t>(B, n_samples - b0));
+        rc = fmgmc_cnn_make_data(ctx, level, S, xi + size_t(b0) * M, xc, tc, xf, tf, nullptr);
+        if (rc != FMGMC_OK && rc != FMGMC_ENOTCONV) break;
+        double loss = 0.0;
+        if ((rc = cnn_grad_impl(cnn, n, S, xf, tf, FMGMC_CNN_LOSS_RESIDUAL, &loss, nullptr)) != FMGMC_OK) break;
+        if ((rc = cnn_adam_impl(cnn, lr, nullptr)) != FMGMC_OK) break;
+        if (loss_hist) loss_hist[h++] = loss;
+        if (coarse) {
+            if ((rc = cnn_grad_impl(cnn, nc, S, xc, tc, FMGMC_CNN_LOSS_RESIDUAL, &loss, nullptr)) != FMGMC_OK)
+                break;
+            if ((rc = cnn_adam_impl(cnn, lr, nullptr)) != FMGMC_OK) break;
+            if (loss_hist) loss_hist[h++] = loss;
+        }
+    }
+    (void)hipStreamSynchronize(nullptr);
+    dfree(xf);
+    dfree(tf);
+    dfree(xc);
+    dfree(tc);
+    return rc == FMGMC_ENOTCONV ? FMGMC_OK : rc;
 }
 
 int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf, const double *const *qc,

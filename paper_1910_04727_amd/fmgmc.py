@@ -62,6 +62,19 @@ _SIGS = {
     "fmgmc_set_schedule": (C.c_int, [_VP, C.c_int32, _VP]),
     "fmgmc_profile_enable": (C.c_int, [_VP, C.c_int32]),
     "fmgmc_profile_read": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
+    "fmgmc_cnn_create": (C.c_int, [C.POINTER(_VP), C.c_uint64, C.c_int32]),
+    "fmgmc_cnn_destroy": (C.c_int, [_VP]),
+    "fmgmc_cnn_get_params": (C.c_int, [_VP, _VP]),
+    "fmgmc_cnn_set_params": (C.c_int, [_VP, _VP]),
+    "fmgmc_cnn_save": (C.c_int, [_VP, C.c_char_p]),
+    "fmgmc_cnn_load": (C.c_int, [_VP, C.c_char_p]),
+    "fmgmc_cnn_forward": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, C.c_int32, _VP]),
+    "fmgmc_cnn_grad": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, C.c_int32, C.POINTER(C.c_double), _VP,
+                                 _VP]),
+    "fmgmc_cnn_adam": (C.c_int, [_VP, C.c_double, _VP]),
+    "fmgmc_cnn_make_data": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "fmgmc_cnn_train": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, _VP, C.c_int32, C.c_double, _VP]),
+    "fmgmc_set_warm_start": (C.c_int, [_VP, _VP, C.c_int32]),
     "fmgmc_last_error": (C.c_char_p, []),
     "fmgmc_version": (C.c_int, []),
 }
@@ -157,7 +170,7 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    PROF_KINDS = ("pre", "post", "ir", "kl", "small")
+    PROF_KINDS = ("pre", "post", "ir", "kl", "small", "cnn")
 
     def profile(self, enable=True):
         _check(lib().fmgmc_profile_enable(self._h, 1 if enable else 0))
@@ -218,6 +231,90 @@ class Context:
     def set_schedule(self, level, check_every=1, graphs=0, batch=0):
         p = np.array([check_every, graphs, batch], np.int32)
         _check(lib().fmgmc_set_schedule(self._h, level, _ptr(p)))
+
+
+    def set_warm_start(self, cnn, min_n=256):
+        """Warm-start QoI stages with n >= min_n from `cnn` (None: off)."""
+        self._warm = cnn  # keep the network alive while the context uses it
+        _check(lib().fmgmc_set_warm_start(self._h, cnn._h if cnn is not None else None, min_n))
+
+    def make_data(self, level, xi, x_coarse, t_coarse, x_fine, t_fine, stream=None):
+        """Training pairs of the two QoI stages (device float32 buffers)."""
+        return _check(lib().fmgmc_cnn_make_data(self._h, level, xi.shape[0], _ptr(xi), _ptr(x_coarse),
+                                                _ptr(t_coarse), _ptr(x_fine), _ptr(t_fine), _stream_ptr(stream)),
+                      (ENOTCONV,))
+
+    def train_cnn(self, cnn, level, xi, batch, lr):
+        """Native training loop; returns the loss after every Adam step."""
+        n = xi.shape[0]
+        steps = -(-n // min(batch, n))
+        hist = np.full(steps * (2 if level >= 1 else 1), np.nan)
+        _check(lib().fmgmc_cnn_train(self._h, cnn._h, level, n, _ptr(xi), batch, lr, _ptr(hist)))
+        return hist[np.isfinite(hist)]
+
+
+class Cnn:
+    """The warm-start network (2 -> 32 -> 4 residual 32 -> 1, 3x3)."""
+    NPARAMS = 37889
+
+    def __init__(self, seed=0, device=0, path=None):
+        h = _VP()
+        _check(lib().fmgmc_cnn_create(C.byref(h), seed, device))
+        self._h = h
+        if path is not None:
+            self.load(path)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fmgmc_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def params(self):
+        out = np.zeros(self.NPARAMS, np.float32)
+        _check(lib().fmgmc_cnn_get_params(self._h, _ptr(out)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32) if isinstance(theta, np.ndarray) else theta
+        _check(lib().fmgmc_cnn_set_params(self._h, _ptr(theta)))
+
+    def save(self, path):
+        _check(lib().fmgmc_cnn_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        _check(lib().fmgmc_cnn_load(self._h, os.fsencode(path)))
+
+    def forward(self, x, y, prec="bf16", stream=None):
+        """x [B][2][n][n], y [B][n][n]: device float32 tensors."""
+        _check(lib().fmgmc_cnn_forward(self._h, x.shape[-1], x.shape[0], _ptr(x), _ptr(y),
+                                       CNN_PREC[prec], _stream_ptr(stream)))
+        return y
+
+    def grad(self, x, t=None, grad=None, loss="error", stream=None):
+        """Loss ("error" against targets t, or "residual") and gradient into `grad` if given."""
+        val = C.c_double()
+        _check(lib().fmgmc_cnn_grad(self._h, x.shape[-1], x.shape[0], _ptr(x), _ptr(t), CNN_LOSS[loss],
+                                    C.byref(val), _ptr(grad), _stream_ptr(stream)))
+        return val.value
+
+    def adam(self, lr, stream=None):
+        _check(lib().fmgmc_cnn_adam(self._h, lr, _stream_ptr(stream)))
+
+
+CNN_PREC = {"fp32": 0, "bf16": 1}
+CNN_LOSS = {"error": 0, "residual": 1}
 
 
 def _check_count(rc):
