@@ -37,7 +37,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(torch, fmgmc, xi_dev, solver, args):
+WEIGHTS = os.path.join(ROOT, "paper_1910_04727_amd", "weights", "cnn_cfg2.bin")
+
+
+def run_form(torch, fmgmc, xi_dev, form, args):
+    """form: fp32_ir, fp64, or nn_warm (fp32_ir started from the trained network on 256^2 and 512^2)."""
+    solver = "fp32_ir" if form == "nn_warm" else form
     S = xi_dev.shape[0]
     qf = torch.zeros(S, dtype=torch.float64, device="cuda")
     qc = torch.zeros_like(qf)
@@ -45,6 +50,10 @@ def run_form(torch, fmgmc, xi_dev, solver, args):
     fl = torch.zeros(S, dtype=torch.uint8, device="cuda")
     ctx = fmgmc.Context(**CFG, solver=solver, rel_tol=args.tol, max_batch=args.batch,
                         inner_cycles=args.inner, max_cycles=60)
+    net = None
+    if form == "nn_warm":
+        net = fmgmc.Cnn(path=WEIGHTS)
+        ctx.set_warm_start(net, min_n=256)
 
     def step():
         rc = ctx.solve_level(LEVEL, xi_dev, qf, qc, cyc, fl)
@@ -53,18 +62,20 @@ def run_form(torch, fmgmc, xi_dev, solver, args):
 
     for w in range(args.warmup):
         step()
-        log(f"[{solver}] warmup {w + 1}/{args.warmup} done")
+        log(f"[{form}] warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         rc, est = step()
-        log(f"[{solver}] step {k + 1}/{args.steps} done")
+        log(f"[{form}] step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
     prof = ctx.profile_read()
     ctx.close()
+    if net is not None:
+        net.close()
     dt = (t1 - t0) / args.steps
     c = cyc.cpu().numpy()
     return dict(samples_per_s=S / dt, ms_per_step=1e3 * dt, rc=int(rc),
@@ -375,7 +386,70 @@ def report_cfg4(torch, fmgmc, inputs, args):
                                    f"{ns} (65536 total), FP32+IR to rel-res 1e-10, batch 512"}}
 
 
-REPORTS = {"cfg1": report_cfg1, "cfg2": report_cfg2, "cfg3": report_cfg3, "cfg4": report_cfg4}
+def report_cfg5(torch, fmgmc, inputs, args):
+    """Learned warm start at 256^2 / 512^2: train on the method's own solutions, then
+    compare FMG from the network's start with plain FMG on unseen samples."""
+    cfg = dict(CFG)
+    ntr, bt = args.cnn_train, 8
+    xi_tr = _dev(torch, inputs.mc_normals_blocked(0, ntr, cfg["n_modes"], config=5, level=LEVEL,
+                                                  purpose=inputs.PURPOSE_CNN_TRAIN))
+    xi_te = _dev(torch, inputs.mc_normals(1024, cfg["n_modes"], config=5, level=LEVEL,
+                                          purpose=inputs.PURPOSE_CNN_TEST))
+    res = {}
+    with fmgmc.Context(**cfg, solver="fp32_ir", max_batch=args.batch, max_cycles=60) as ctx, \
+            fmgmc.Cnn(seed=5) as net:
+        hist = []
+        t0 = _t(torch)
+        chunk = 1024
+        for c0 in range(0, ntr, chunk):
+            lr = 1e-3 if c0 < ntr // 2 else 3e-4
+            hist.extend(ctx.train_cnn(net, LEVEL, xi_tr[c0:c0 + chunk], batch=bt, lr=lr).tolist())
+            log(f"cfg5 trained on {min(c0 + chunk, ntr)}/{ntr} samples, residual loss {np.mean(hist[-16:]):.4f}")
+        t_train = _t(torch) - t0
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        net.save(os.path.join(ROOT, "gpurun_out", "cnn_cfg2.bin"))
+        S = xi_te.shape[0]
+        outs = {}
+        for name, cnn in (("plain", None), ("warm", net)):
+            ctx.set_warm_start(cnn, min_n=256)
+            qf, qc, cyc, fl = _bufs(torch, S)
+            ctx.solve_level(LEVEL, xi_te, qf, qc, cyc, fl)
+            t0 = _t(torch)
+            for _ in range(args.steps):
+                ctx.solve_level(LEVEL, xi_te, qf, qc, cyc, fl)
+            dt = (_t(torch) - t0) / args.steps
+            ctx.profile(True)
+            ctx.solve_level(LEVEL, xi_te, qf, qc, cyc, fl)
+            ctx.profile(False)
+            prof = ctx.profile_read()
+            outs[name] = (qf.cpu().numpy(), qc.cpu().numpy(), cyc.cpu().numpy(), fl.cpu().numpy(), dt, prof)
+    p, w = outs["plain"], outs["warm"]
+    ep = fmgmc.estimate([p[0]], [p[1]])["mean"]
+    ew = fmgmc.estimate([w[0]], [w[1]])["mean"]
+    cms, cn, cfl = w[5]["cnn"]
+    hist = np.asarray(hist)
+    res = {
+        "train_samples": ntr, "train_stage_solutions": 2 * ntr, "train_seconds": round(t_train, 2),
+        "adam_steps": int(hist.size), "residual_loss_first_last": [float(hist[:32].mean()), float(hist[-32:].mean())],
+        "cycles_plain": [round(float(x), 4) for x in p[2].mean(0)],
+        "cycles_warm": [round(float(x), 4) for x in w[2].mean(0)],
+        "cycles_saved": [round(float(x), 4) for x in p[2].mean(0) - w[2].mean(0)],
+        "warm_rejected": int(((w[3] & 4) != 0).sum()), "flagged": int((w[3] & 3).sum()),
+        "samples_per_s_plain": round(S / p[4], 1), "samples_per_s_warm": round(S / w[4], 1),
+        "cnn_ms_per_solve": round(cms, 3), "cnn_tflops": round(cfl / (cms * 1e-3) / 1e12, 2) if cn else None,
+        "estimate_plain": ep, "estimate_warm": ew, "estimate_rel_diff": abs(ew - ep) / abs(ep),
+        "max_sample_rel_diff_qf": float(np.max(np.abs(w[0] - p[0]) / np.abs(p[0]))),
+        "max_sample_rel_diff_qc": float(np.max(np.abs(w[1] - p[1]) / np.abs(p[1]))),
+    }
+    return {"metric": "cfg5 learned warm start at 256^2/512^2", "value": res["samples_per_s_warm"],
+            "unit": "samples/s", "report": res,
+            "config": {"workload": f"level 4 of the 5-level config (512^2, coarse stage 256^2), trained on {ntr} "
+                                   "samples (two stage solutions each), 1024 unseen test samples, FP32+IR to 1e-10, "
+                                   "warm start on both QoI stages"}}
+
+
+REPORTS = {"cfg1": report_cfg1, "cfg2": report_cfg2, "cfg3": report_cfg3, "cfg4": report_cfg4,
+           "cfg5": report_cfg5}
 
 
 def main():
@@ -389,9 +463,10 @@ def main():
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--inner", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--forms", default="fp32_ir,fp64")
+    ap.add_argument("--forms", default="fp32_ir,fp64,nn_warm")
     ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cnn-train", type=int, default=16384, help="cfg5: level-4 training samples")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -454,6 +529,15 @@ def main():
             "roofline": roofline(f, args.steps),
             "kl_tflops": round(kl_flops / (kl_ms * 1e-3) / 1e12, 2) if kl_n else None,
         }
+        cnn_ms, cnn_n, cnn_flops = f["prof"]["cnn"]
+        if cnn_n:
+            out["forms"][k]["cnn_tflops"] = round(cnn_flops / (cnn_ms * 1e-3) / 1e12, 2)
+            out["forms"][k]["cnn_ms_per_step"] = round(cnn_ms / args.steps, 3)
+    if "nn_warm" in forms and "fp32_ir" in forms:
+        a, b = forms["nn_warm"], forms["fp32_ir"]
+        out["forms"]["nn_warm_cycles_saved"] = [round(b["cycles_coarse_mean"] - a["cycles_coarse_mean"], 4),
+                                                round(b["cycles_fine_mean"] - a["cycles_fine_mean"], 4)]
+        out["forms"]["nn_warm_vs_fp32_ir_max_rel_qf_diff"] = float(np.max(np.abs(a["qf"] - b["qf"]) / np.abs(b["qf"])))
     if "fp32_ir" in forms and "fp64" in forms:
         a, b = forms["fp32_ir"], forms["fp64"]
         out["forms"]["ir_vs_fp64_speedup"] = round(a["samples_per_s"] / b["samples_per_s"], 3)
