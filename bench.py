@@ -48,8 +48,9 @@ def run_form(torch, fmgmc, xi_dev, form, args):
     qc = torch.zeros_like(qf)
     cyc = torch.zeros((S, 2), dtype=torch.int32, device="cuda")
     fl = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    nu1, nu2 = (int(v) for v in args.nu.split(",")) if solver == "fp32_ir" else (2, 2)
     ctx = fmgmc.Context(**CFG, solver=solver, rel_tol=args.tol, max_batch=args.batch,
-                        inner_cycles=args.inner, max_cycles=60)
+                        inner_cycles=args.inner, max_cycles=60, nu1=nu1, nu2=nu2, w_max_n=args.wmax)
     net = None
     if form == "nn_warm":
         net = fmgmc.Cnn(path=WEIGHTS)
@@ -462,6 +463,8 @@ def main():
     ap.add_argument("--samples", type=int, default=4096)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--inner", type=int, default=1)
+    ap.add_argument("--wmax", type=int, default=64, help="W-cycle coarse corrections on grids n <= wmax")
+    ap.add_argument("--nu", default="2,2", help="pre,post smoothing sweeps of the FP32 cycles (1..4)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--forms", default="fp32_ir,fp64,nn_warm")
     ap.add_argument("--cpu-samples", type=int, default=128)
@@ -515,7 +518,7 @@ def main():
         "config": {"workload": f"finest MLMC level {N}^2 (coarse stage {N // 2}^2) of the 5-level config, "
                                f"sigma2=1, corr_len=0.2, 256 KL modes, {args.samples} samples, "
                                f"rel-res {args.tol:g}, form {head}",
-                   "batch": args.batch, "inner_cycles": args.inner},
+                   "batch": args.batch, "inner_cycles": args.inner, "nu_fp32": args.nu},
         "roofline": roofline(H, args.steps),
     }
     out["forms"] = {}

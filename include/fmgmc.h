@@ -82,7 +82,8 @@ typedef struct {
 typedef struct {
     int32_t solver;        /* FMGMC_SOLVER_FP64 or FMGMC_SOLVER_FP32_IR */
     int32_t kl_prec;       /* FMGMC_KL_FP64 / FP32 / BF16 (arithmetic of the KL contraction) */
-    int32_t nu1, nu2;      /* pre/post red-black Gauss-Seidel sweeps per V-cycle, 1..2 */
+    int32_t nu1, nu2;      /* pre/post red-black Gauss-Seidel sweeps per V-cycle: 1..2 (FP64),
+                              1..4 (FP32_IR, whose cycles run in FP32) */
     int32_t max_cycles;    /* cap on V-cycles per QoI stage (>= 1) */
     int32_t inner_cycles;  /* FP32 V-cycles per FP64 refinement step (FP32_IR), >= 1 */
     int32_t max_batch;     /* samples resident on the device at once (0 = library default) */

@@ -632,7 +632,9 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
     if (nf > 1024) return FMGMC_EINVAL;
     if (o->solver != FMGMC_SOLVER_FP64 && o->solver != FMGMC_SOLVER_FP32_IR) return FMGMC_EINVAL;
     if (o->kl_prec < FMGMC_KL_FP64 || o->kl_prec > FMGMC_KL_BF16) return FMGMC_EINVAL;
-    if (o->nu1 < 1 || o->nu1 > 2 || o->nu2 < 1 || o->nu2 > 2 || o->max_cycles < 1 || !(o->rel_tol > 0))
+    // smoothing sweeps: 1..2 in FP64 cycles, 1..4 in FP32 cycles
+    const int nu_max = o->solver == FMGMC_SOLVER_FP32_IR ? 4 : 2;
+    if (o->nu1 < 1 || o->nu1 > nu_max || o->nu2 < 1 || o->nu2 > nu_max || o->max_cycles < 1 || !(o->rel_tol > 0))
         return FMGMC_EINVAL;
     if (o->solver == FMGMC_SOLVER_FP32_IR && h->n0 < 8) return FMGMC_EINVAL;  // QoI stages need n >= 8
     if (o->max_batch < 0 || o->w_max_n < 0) return FMGMC_EINVAL;

@@ -17,7 +17,12 @@ namespace {
 constexpr int TS = 64;     // samples per tile
 constexpr int TC = 64;     // cells per tile
 constexpr int TM = 64;     // modes per LDS chunk
-constexpr int PAD = 1;     // LDS row padding (bank spread)
+// LDS row strides (elements) chosen so that the MFMA operand reads hit
+// distinct banks: A reads 16 rows x 4 k-columns, B reads 4 k-rows x 16
+// columns. FP64 (8-byte reads, 32 lanes per pass): A stride = 2 mod 32
+// doubles, B stride = 16 mod 32. FP32: A stride = 4 mod 64, B stride = 16 mod 64.
+template <typename T> constexpr int xstr() { return sizeof(T) == 8 ? TM + 2 : TM + 4; }
+constexpr int BSTR = TC + 16;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -41,31 +46,18 @@ __device__ __forceinline__ void store_pyramid(const KLArgs &A, int S, int s, int
     }
 }
 
-// B slice for modes [m0, m0+TM) and cells [c0, c0+TC): Bt[m][c]. When the
-// cell tile lies in one grid row j (n >= TC), rowf[m] = sqrt(lambda_m) phi_{b_m}(y_j)
-// and ia[m] = a_m * n are staged in LDS once per workgroup.
-template <typename TB>
-__device__ __forceinline__ void build_b(const KLArgs &A, int m0, int c0, TB *Bt, const double *rowf,
-                                       const int *ia) {
-    const int n = A.n;
-    if (rowf) {
-        const int i0 = c0 % n;
-        for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
-            const int mm = e / TC, cc = e % TC, m = m0 + mm;
-            Bt[mm * (TC + PAD) + cc] = TB((m < A.M) ? rowf[m] * A.phi[ia[m] + i0 + cc] : 0.0);
-        }
-        return;
-    }
-    for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
-        const int mm = e / TC, cc = e % TC;
-        const int m = m0 + mm, c = c0 + cc;
-        double v = 0.0;
-        if (m < A.M && c < n * n) {
-            const int i = c % n, j = c / n;
-            v = A.sqrtlam[m] * A.phi[size_t(A.ma[m]) * n + i] * A.phi[size_t(A.mb[m]) * n + j];
-        }
-        Bt[mm * (TC + PAD) + cc] = TB(v);
-    }
+// Element e of the 64-mode x 64-cell slice Bt[m][c] (modes m0.., cells c0..):
+// sqrt(lambda_m) phi_{a_m}(x_i) phi_{b_m}(y_j). When the cell tile lies in one
+// grid row j (n >= TC), rowf[m] = sqrt(lambda_m) phi_{b_m}(y_j) and ia[m] = a_m n
+// are staged in LDS once per workgroup.
+__device__ __forceinline__ double b_elem(const KLArgs &A, int m0, int c0, int e, const double *rowf, const int *ia) {
+    const int n = A.n, mm = e / TC, cc = e % TC, m = m0 + mm;
+    if (m >= A.M) return 0.0;
+    if (rowf) return rowf[m] * A.phi[ia[m] + (c0 % n) + cc];
+    const int c = c0 + cc;
+    if (c >= n * n) return 0.0;
+    const int i = c % n, j = c / n;
+    return A.sqrtlam[m] * A.phi[size_t(A.ma[m]) * n + i] * A.phi[size_t(A.mb[m]) * n + j];
 }
 
 // stages rowf / ia for a one-row tile; returns whether it applies
@@ -80,40 +72,60 @@ __device__ __forceinline__ bool stage_row(const KLArgs &A, int c0, double *rowf,
     return true;
 }
 
-template <typename TA>
-__device__ __forceinline__ void load_xi(const KLArgs &A, int S, int s0, int m0, TA *Xs) {
-    for (int e = threadIdx.x; e < TS * TM; e += blockDim.x) {
-        const int ss = e / TM, mm = e % TM;
-        const int s = s0 + ss, m = m0 + mm;
-        const double v = (s < S && m < A.M) ? A.xi[size_t(s) * A.M + m] : 0.0;
-        Xs[ss * (TM + PAD) + mm] = TA(v);
-    }
+__device__ __forceinline__ double xi_elem(const KLArgs &A, int S, int s0, int m0, int e) {
+    const int s = s0 + e / TM, m = m0 + e % TM;
+    return (s < S && m < A.M) ? A.xi[size_t(s) * A.M + m] : 0.0;
 }
+
+// Both MFMA forms share the schedule: the A (xi) and B (Phi) values of chunk
+// k + 1 are loaded into registers while the matrix cores work on chunk k from
+// LDS, so global latency hides behind the contraction.
+constexpr int PER = TS * TM / 256;  // elements per thread per chunk (both tiles are 64 x 64)
 
 // FP64: v_mfma_f64_16x16x4_f64. Lane l: A[row l%16][k l/16], B[k l/16][col l%16];
 // output register v of lane l holds row 4 v + l/16, column l%16 (one row per
 // 16-lane group per register, unlike the FP32/BF16 16x16 forms).
 __global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
-    __shared__ double Xs[TS * (TM + PAD)];
-    __shared__ double Bt[TM * (TC + PAD)];
+    constexpr int XSTR = xstr<double>();
+    __shared__ double Xs[TS * XSTR];
+    __shared__ double Bt[TM * BSTR];
     extern __shared__ double rowf[];  // [M] then int ia[M]
     int *ia = reinterpret_cast<int *>(rowf + A.M);
     const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const bool row = stage_row(A, c0, rowf, ia);
+    __syncthreads();
+    const double *rf = row ? rowf : nullptr;
+    double xr[PER], br[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        xr[k] = xi_elem(A, S, s0, 0, t + 256 * k);
+        br[k] = b_elem(A, 0, c0, t + 256 * k, rf, ia);
+    }
     d4 acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     for (int m0 = 0; m0 < A.M; m0 += TM) {
         __syncthreads();
-        load_xi(A, S, s0, m0, Xs);
-        build_b(A, m0, c0, Bt, row ? rowf : nullptr, ia);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = t + 256 * k;
+            Xs[(e / TM) * XSTR + e % TM] = xr[k];
+            Bt[(e / TC) * BSTR + e % TC] = br[k];
+        }
         __syncthreads();
+        if (m0 + TM < A.M) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                xr[k] = xi_elem(A, S, s0, m0 + TM, t + 256 * k);
+                br[k] = b_elem(A, m0 + TM, c0, t + 256 * k, rf, ia);
+            }
+        }
 #pragma unroll 4
         for (int kk = 0; kk < TM / 4; ++kk) {
-            const double a = Xs[(16 * w + (l & 15)) * (TM + PAD) + 4 * kk + (l >> 4)];
+            const double a = Xs[(16 * w + (l & 15)) * XSTR + 4 * kk + (l >> 4)];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double b = Bt[(4 * kk + (l >> 4)) * (TC + PAD) + 16 * q + (l & 15)];
+                const double b = Bt[(4 * kk + (l >> 4)) * BSTR + 16 * q + (l & 15)];
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
             }
         }
@@ -128,26 +140,46 @@ __global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
 // FP32: v_mfma_f32_16x16x4_f32, same operand layout as the FP64 form; output
 // register v of lane l holds row 4 (l/16) + v, column l%16.
 __global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
-    __shared__ float Xs[TS * (TM + PAD)];
-    __shared__ float Bt[TM * (TC + PAD)];
+    constexpr int XSTR = xstr<float>();
+    __shared__ float Xs[TS * XSTR];
+    __shared__ float Bt[TM * BSTR];
     extern __shared__ double rowf[];  // [M] then int ia[M]
     int *ia = reinterpret_cast<int *>(rowf + A.M);
     const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const bool row = stage_row(A, c0, rowf, ia);
+    __syncthreads();
+    const double *rf = row ? rowf : nullptr;
+    float xr[PER], br[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        xr[k] = float(xi_elem(A, S, s0, 0, t + 256 * k));
+        br[k] = float(b_elem(A, 0, c0, t + 256 * k, rf, ia));
+    }
     f4 acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
     for (int m0 = 0; m0 < A.M; m0 += TM) {
         __syncthreads();
-        load_xi(A, S, s0, m0, Xs);
-        build_b(A, m0, c0, Bt, row ? rowf : nullptr, ia);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = t + 256 * k;
+            Xs[(e / TM) * XSTR + e % TM] = xr[k];
+            Bt[(e / TC) * BSTR + e % TC] = br[k];
+        }
         __syncthreads();
+        if (m0 + TM < A.M) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                xr[k] = float(xi_elem(A, S, s0, m0 + TM, t + 256 * k));
+                br[k] = float(b_elem(A, m0 + TM, c0, t + 256 * k, rf, ia));
+            }
+        }
 #pragma unroll 4
         for (int kk = 0; kk < TM / 4; ++kk) {
-            const float a = Xs[(16 * w + (l & 15)) * (TM + PAD) + 4 * kk + (l >> 4)];
+            const float a = Xs[(16 * w + (l & 15)) * XSTR + 4 * kk + (l >> 4)];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float b = Bt[(4 * kk + (l >> 4)) * (TC + PAD) + 16 * q + (l & 15)];
+                const float b = Bt[(4 * kk + (l >> 4)) * BSTR + 16 * q + (l & 15)];
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
             }
         }

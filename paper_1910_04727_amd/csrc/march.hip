@@ -16,6 +16,8 @@
 // (so boundary neighbours contribute nothing without a branch); per-row
 // coefficients live in a register ring. One barrier per row step: every
 // cross-lane read in step F is of data written before step F's barrier.
+#include <type_traits>
+
 #include "common.h"
 
 namespace fmgmc {
@@ -75,10 +77,14 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
     return t;
 }
 
+// rows of x alive at one step: the row being loaded, the NH rows being swept,
+// their lower neighbour and the row whose residual is formed
+constexpr int march_ring_rows(int nh) { return nh + 3 <= 8 ? 8 : 16; }
+
 template <typename T, int NH, bool CK, int INIT, bool RHSA, int OUT>
 __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     constexpr int U = NH + 1;    // register ring depth = prefetch distance = unroll
-    constexpr int RX = 8;        // LDS x ring rows (>= NH + 3), power of two
+    constexpr int RX = march_ring_rows(NH);  // LDS x ring rows (>= NH + 3), power of two
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
     constexpr bool LX = (INIT == INIT_LOAD || INIT == INIT_PROLONG);
@@ -228,14 +234,20 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                     T *row = xs + (r & (RX - 1)) * XS + 2;
                     const T *up = xs + ((r + 1) & (RX - 1)) * XS + 2;
                     const T *dn = xs + ((r - 1) & (RX - 1)) * XS + 2;
+                    // cell pairs are read and written whole: consecutive lanes touch
+                    // consecutive 2-cell words, which keeps the LDS accesses
+                    // conflict-free; the partner cell is written back unchanged
+                    const V2<T> own = ld2(row + 2 * l), vd = ld2(dn + 2 * l), vu = ld2(up + 2 * l);
                     if (((t - 1 + r) & 1) == 0) {  // this lane's red/black cell is column 2l
-                        const T v = (((rb0[sr] + rw[sr] * row[2 * l - 1]) + rm[sr] * row[2 * l + 1]) +
-                                     rs0[sr] * dn[2 * l] + rn0[sr] * up[2 * l]) * ri0[sr];
-                        row[2 * l] = v;
+                        const T west = ld2(row + 2 * l - 2).b;
+                        const T v = (((rb0[sr] + rw[sr] * west) + rm[sr] * own.b) + rs0[sr] * vd.a +
+                                     rn0[sr] * vu.a) * ri0[sr];
+                        st2(row + 2 * l, v, own.b);
                     } else {                        // column 2l + 1
-                        const T v = (((rb1[sr] + rm[sr] * row[2 * l]) + re[sr] * row[2 * l + 2]) +
-                                     rs1[sr] * dn[2 * l + 1] + rn1[sr] * up[2 * l + 1]) * ri1[sr];
-                        row[2 * l + 1] = v;
+                        const T east = ld2(row + 2 * l + 2).a;
+                        const T v = (((rb1[sr] + rm[sr] * own.a) + re[sr] * east) + rs1[sr] * vd.b +
+                                     rn1[sr] * vu.b) * ri1[sr];
+                        st2(row + 2 * l, own.a, v);
                     }
                 }
             }
@@ -247,13 +259,15 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                     const T *row = xs + (r & (RX - 1)) * XS + 2;
                     const T *up = xs + ((r + 1) & (RX - 1)) * XS + 2;
                     const T *dn = xs + ((r - 1) & (RX - 1)) * XS + 2;
-                    const T x0 = row[2 * l], x1 = row[2 * l + 1];
+                    const V2<T> own = ld2(row + 2 * l), vd = ld2(dn + 2 * l), vu = ld2(up + 2 * l);
+                    const T x0 = own.a, x1 = own.b;
+                    const T west = ld2(row + 2 * l - 2).b, east = ld2(row + 2 * l + 2).a;
                     const T d0 = ((rw[sr] + rm[sr]) + rs0[sr]) + rn0[sr];
                     const T d1 = ((rm[sr] + re[sr]) + rs1[sr]) + rn1[sr];
-                    const T res0 = (((rb0[sr] + rw[sr] * row[2 * l - 1]) + rm[sr] * x1) + rs0[sr] * dn[2 * l] +
-                                    rn0[sr] * up[2 * l]) - d0 * x0;
-                    const T res1 = (((rb1[sr] + rm[sr] * x0) + re[sr] * row[2 * l + 2]) + rs1[sr] * dn[2 * l + 1] +
-                                    rn1[sr] * up[2 * l + 1]) - d1 * x1;
+                    const T res0 = (((rb0[sr] + rw[sr] * west) + rm[sr] * x1) + rs0[sr] * vd.a + rn0[sr] * vu.a) -
+                                   d0 * x0;
+                    const T res1 = (((rb1[sr] + rm[sr] * x0) + re[sr] * east) + rs1[sr] * vd.b + rn1[sr] * vu.b) -
+                                   d1 * x1;
                     if (OUT & OUT_RR) rr += res0 * res0 + res1 * res1;
                     if (OUT & OUT_RESTRICT) {
                         if (r & 1) A.bc[cbase + size_t(r >> 1) * nc + l] = ((rprev + res0) + res1);
@@ -267,7 +281,8 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                 if (r >= 0 && r < n) {
                     const int sr = (u + 2 * U - NH) % U;
                     const T *row = xs + (r & (RX - 1)) * XS + 2;
-                    const T x0 = row[2 * l], x1 = row[2 * l + 1];
+                    const V2<T> xv = ld2(row + 2 * l);
+                    const T x0 = xv.a, x1 = xv.b;
                     st2(A.x + base + size_t(r) * n + 2 * l, x0, x1);
                     if ((OUT & OUT_Q) && last) q += re[sr] * (x1 - gE);
                 }
@@ -286,7 +301,8 @@ template <typename T, int NH>
 static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool rhsa, int out,
                           hipStream_t st) {
     const int n = a.n;
-    const size_t lds = (size_t(8) * (n + 4) + 4 * size_t(n) + 4 * size_t(n / 2) + 16) * sizeof(T);
+    const size_t lds =
+        (size_t(march_ring_rows(NH)) * (n + 4) + 4 * size_t(n) + 4 * size_t(n / 2) + 16) * sizeof(T);
     dim3 grid(S), block(n / 2);
 #define FMGMC_MARCH_CASE(CKV, INITV, RHSV, OUTV)                                               \
     if (ck == CKV && init == INITV && rhsa == RHSV && out == (OUTV)) {                         \
@@ -320,7 +336,12 @@ int launch_march(const MarchArgs<T> &a, int S, int nhalf, bool coef_from_k, int 
     if (S <= 0) return FMGMC_OK;
     if (nhalf == 4) return dispatch_march<T, 4>(a, S, coef_from_k, init, rhs_array, out, st);
     if (nhalf == 2) return dispatch_march<T, 2>(a, S, coef_from_k, init, rhs_array, out, st);
-    set_error("launch_march: nu must be 1 or 2");
+    // three and four sweeps: FP32 only (the FP64 register rings would spill)
+    if constexpr (std::is_same<T, float>::value) {
+        if (nhalf == 6) return dispatch_march<T, 6>(a, S, coef_from_k, init, rhs_array, out, st);
+        if (nhalf == 8) return dispatch_march<T, 8>(a, S, coef_from_k, init, rhs_array, out, st);
+    }
+    set_error("launch_march: nu must be 1 or 2 (FP64) or 1 to 4 (FP32)");
     return FMGMC_EINVAL;
 }
 

@@ -76,32 +76,53 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
     if (i == n - 1) A.q[s] = q;
 }
 
+// One thread per coarse cell (I, J): its 2 x 2 fine cells from the 3 x 3
+// coarse neighbourhood (ghost values at the boundary), written as two
+// 16-byte row pairs.
 template <typename TS>
 __global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE) {
     const int s = blockIdx.y;
     if (active && active[s] == 0) return;
+    const int nc = n / 2;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n * n) return;
-    const int i = c % n, j = c / n, nc = n / 2;
+    if (c >= nc * nc) return;
+    const int I = c % nc, J = c / nc;
     const TS *x = xc + size_t(s) * nc * nc;
-    const int I = i >> 1, J = j >> 1, di = (i & 1) ? 1 : -1, dj = (j & 1) ? 1 : -1;
-    p[size_t(s) * n * n + c] =
-        (9.0 * ghost_d(x, nc, I, J, pW, pE) + 3.0 * ghost_d(x, nc, I + di, J, pW, pE) +
-         3.0 * ghost_d(x, nc, I, J + dj, pW, pE) + ghost_d(x, nc, I + di, J + dj, pW, pE)) / 16.0;
+    double v[3][3];
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) v[dj + 1][di + 1] = ghost_d(x, nc, I + di, J + dj, pW, pE);
+    double *o = p + size_t(s) * n * n + size_t(2 * J) * n + 2 * I;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int dj = b ? 1 : -1;
+        double out[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int di = a ? 1 : -1;
+            out[a] = (9.0 * v[1][1] + 3.0 * v[1][1 + di] + 3.0 * v[1 + dj][1] + v[1 + dj][1 + di]) / 16.0;
+        }
+        *reinterpret_cast<double2 *>(o + size_t(b) * n) = make_double2(out[0], out[1]);
+    }
 }
 
+// one workgroup per sample, lanes over the rows (column 0 and n-1 of each row)
 template <typename T>
-__global__ void k_bnorm(int n, const T *K, double pW, double pE, double *bn, int S) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+__global__ __launch_bounds__(256) void k_bnorm(int n, const T *K, double pW, double pE, double *bn) {
+    __shared__ double red[4];
+    const int s = blockIdx.x;
     const T *k = K + size_t(s) * n * n;
     double acc = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const double bw = 2.0 * double(k[size_t(j) * n]) * pW;
         const double be = 2.0 * double(k[size_t(j) * n + n - 1]) * pE;
         acc += bw * bw + be * be;
     }
-    bn[s] = sqrt(acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) bn[s] = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 __global__ __launch_bounds__(1024) void k_check(CheckArgs A, int S) {
@@ -230,7 +251,7 @@ template <typename TS>
 int launch_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE, int S,
                     hipStream_t st) {
     if (S <= 0) return FMGMC_OK;
-    dim3 grid((n * n + 255) / 256, S);
+    dim3 grid((n * n / 4 + 255) / 256, S);
     hipLaunchKernelGGL(k_interp64<TS>, grid, dim3(256), 0, st, n, xc, p, active, pW, pE);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
@@ -240,7 +261,7 @@ template int launch_interp64<double>(int, const double *, double *, const int32_
 template <typename T>
 int launch_bnorm(int n, const T *K, double pW, double pE, double *bn, int S, hipStream_t st) {
     if (S <= 0) return FMGMC_OK;
-    hipLaunchKernelGGL(k_bnorm<T>, dim3((S + 255) / 256), dim3(256), 0, st, n, K, pW, pE, bn, S);
+    hipLaunchKernelGGL(k_bnorm<T>, dim3(S), dim3(256), 0, st, n, K, pW, pE, bn);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 template int launch_bnorm<double>(int, const double *, double, double, double *, int, hipStream_t);

@@ -278,12 +278,16 @@ template int launch_small<double>(const SmallArgs<double> &, int, int, bool, int
 template int launch_small<float>(const SmallArgs<float> &, int, int, bool, int, hipStream_t);
 
 // ------------------------------------------------- coarsest operator inverse
+// One wave per sample, the N x N (N = n0^2 <= 16) operator in LDS: assembly
+// (one lane per cell), lower Cholesky column by column (lanes over the rows
+// below the diagonal), the columns of L^{-1} by forward substitution (one
+// lane per column), then A^{-1} = L^{-T} L^{-1} (lanes over the entries).
 template <typename T>
-__global__ void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout, int S) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
+__global__ __launch_bounds__(64) void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout) {
+    __shared__ double L[16 * 16];
+    __shared__ double Li[16 * 16];
+    const int s = blockIdx.x, t = threadIdx.x;
     const int N = n0 * n0;
-    double *L = Lout + size_t(s) * N * N;
     auto fxv = [&](int i, int j) -> double {
         if (from_k) {
             const T *k = K + size_t(s) * N;
@@ -303,46 +307,47 @@ __global__ void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout
         }
         return double(f.fy[size_t(s) * N + j * n0 + i]);
     };
-    for (int c = 0; c < N * N; ++c) L[c] = 0.0;
-    for (int j = 0; j < n0; ++j)
-        for (int i = 0; i < n0; ++i) {
-            const int P = j * n0 + i;
-            const double w = fxv(i, j), e = (i < n0 - 1) ? fxv(i + 1, j) : fxe(j);
-            const double so = fyv(i, j), no = (j < n0 - 1) ? fyv(i, j + 1) : 0.0;
-            L[P * N + P] = ((w + e) + so) + no;
-            if (i > 0) L[P * N + P - 1] = -w;
-            if (j > 0) L[P * N + P - n0] = -so;
-        }
-    // in-place lower Cholesky (only the lower triangle is referenced)
-    for (int c = 0; c < N; ++c) {
-        double d = L[c * N + c];
-        for (int k = 0; k < c; ++k) d -= L[c * N + k] * L[c * N + k];
-        d = sqrt(d);  // NaN for a non-SPD (non-finite) operator; flagged by the residual check
-        L[c * N + c] = d;
-        for (int r = c + 1; r < N; ++r) {
-            double v = L[r * N + c];
-            for (int k = 0; k < c; ++k) v -= L[r * N + k] * L[c * N + k];
-            L[r * N + c] = v / d;
-        }
+    for (int e = t; e < N * N; e += 64) L[e] = 0.0;
+    __syncthreads();
+    if (t < N) {
+        const int P = t, i = P % n0, j = P / n0;
+        const double w = fxv(i, j), e = (i < n0 - 1) ? fxv(i + 1, j) : fxe(j);
+        const double so = fyv(i, j), no = (j < n0 - 1) ? fyv(i, j + 1) : 0.0;
+        L[P * N + P] = ((w + e) + so) + no;
+        if (i > 0) L[P * N + P - 1] = -w;
+        if (j > 0) L[P * N + P - n0] = -so;
     }
-    // explicit inverse A^{-1} = L^{-T} L^{-1}: columns of L^{-1} by forward
-    // substitution into the (now unused) upper triangle workspace W
-    double W[16];  // one column of L^{-1} (N <= 16)
-    double Li[16 * 16];
+    __syncthreads();
     for (int c = 0; c < N; ++c) {
+        if (t == 0) {
+            double d = L[c * N + c];
+            for (int k = 0; k < c; ++k) d -= L[c * N + k] * L[c * N + k];
+            L[c * N + c] = sqrt(d);  // NaN for a non-SPD (non-finite) operator; flagged by the residual check
+        }
+        __syncthreads();
+        if (t > c && t < N) {
+            double v = L[t * N + c];
+            for (int k = 0; k < c; ++k) v -= L[t * N + k] * L[c * N + k];
+            L[t * N + c] = v / L[c * N + c];
+        }
+        __syncthreads();
+    }
+    if (t < N) {
+        const int c = t;  // column c of L^{-1}, kept in Li[.][c]
         for (int r = 0; r < N; ++r) {
             double v = (r == c) ? 1.0 : 0.0;
-            for (int k = c; k < r; ++k) v -= L[r * N + k] * W[k];
-            W[r] = (r < c) ? 0.0 : v / L[r * N + r];
+            for (int k = c; k < r; ++k) v -= L[r * N + k] * Li[k * N + c];
+            Li[r * N + c] = (r < c) ? 0.0 : v / L[r * N + r];
         }
-        for (int r = 0; r < N; ++r) Li[r * N + c] = W[r];
     }
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) {
-            double v = 0.0;
-            for (int k = (i > j ? i : j); k < N; ++k) v += Li[k * N + i] * Li[k * N + j];
-            L[i * N + j] = v;
-        }
+    __syncthreads();
+    double *out = Lout + size_t(s) * N * N;
+    for (int e = t; e < N * N; e += 64) {
+        const int i = e / N, j = e % N;
+        double v = 0.0;
+        for (int k = (i > j ? i : j); k < N; ++k) v += Li[k * N + i] * Li[k * N + j];
+        out[e] = v;
+    }
 }
 
 template <typename T>
@@ -352,7 +357,7 @@ int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, double *L, int S, h
         return FMGMC_EINVAL;
     }
     if (S <= 0) return FMGMC_OK;
-    hipLaunchKernelGGL(k_chol<T>, dim3((S + 63) / 64), dim3(64), 0, st, n0, K, f, from_k, L, S);
+    hipLaunchKernelGGL(k_chol<T>, dim3(S), dim3(64), 0, st, n0, K, f, from_k, L);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
