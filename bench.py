@@ -50,7 +50,8 @@ def run_form(torch, fmgmc, xi_dev, form, args):
     fl = torch.zeros(S, dtype=torch.uint8, device="cuda")
     nu1, nu2 = (int(v) for v in args.nu.split(",")) if solver == "fp32_ir" else (2, 2)
     ctx = fmgmc.Context(**CFG, solver=solver, rel_tol=args.tol, max_batch=args.batch,
-                        inner_cycles=args.inner, max_cycles=60, nu1=nu1, nu2=nu2, w_max_n=args.wmax)
+                        inner_cycles=args.inner, max_cycles=60, nu1=nu1, nu2=nu2, w_max_n=args.wmax,
+                        inner_first=args.inner_first)
     net = None
     if form == "nn_warm":
         net = fmgmc.Cnn(path=WEIGHTS)
@@ -81,7 +82,8 @@ def run_form(torch, fmgmc, xi_dev, form, args):
     c = cyc.cpu().numpy()
     return dict(samples_per_s=S / dt, ms_per_step=1e3 * dt, rc=int(rc),
                 cycles_coarse_mean=float(c[:, 0].mean()), cycles_fine_mean=float(c[:, 1].mean()),
-                cycles_fine_max=int(c[:, 1].max()), flags=int(fl.cpu().numpy().astype(np.int64).sum()),
+                cycles_fine_max=int(c[:, 1].max()), flags=int(((fl.cpu().numpy() & 3) != 0).sum()),
+                warm_rejected=int(((fl.cpu().numpy() & 4) != 0).sum()),
                 estimate=dict(mean_y=est["levels"][0]["mean_y"], var_y=est["levels"][0]["var_y"]),
                 prof=prof, qf=qf.cpu().numpy(), qc=qc.cpu().numpy())
 
@@ -463,7 +465,8 @@ def main():
     ap.add_argument("--samples", type=int, default=4096)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--inner", type=int, default=1)
-    ap.add_argument("--wmax", type=int, default=64, help="W-cycle coarse corrections on grids n <= wmax")
+    ap.add_argument("--inner-first", type=int, default=4, help="FP32 cycles before the first refinement")
+    ap.add_argument("--wmax", type=int, default=32, help="W-cycle coarse corrections on grids n <= wmax")
     ap.add_argument("--nu", default="2,2", help="pre,post smoothing sweeps of the FP32 cycles (1..4)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--forms", default="fp32_ir,fp64,nn_warm")
@@ -518,7 +521,8 @@ def main():
         "config": {"workload": f"finest MLMC level {N}^2 (coarse stage {N // 2}^2) of the 5-level config, "
                                f"sigma2=1, corr_len=0.2, 256 KL modes, {args.samples} samples, "
                                f"rel-res {args.tol:g}, form {head}",
-                   "batch": args.batch, "inner_cycles": args.inner, "nu_fp32": args.nu},
+                   "batch": args.batch, "inner_cycles": args.inner, "inner_first": args.inner_first,
+                   "w_max_n": args.wmax, "nu_fp32": args.nu},
         "roofline": roofline(H, args.steps),
     }
     out["forms"] = {}
@@ -529,6 +533,7 @@ def main():
             "cycles_coarse_mean": round(f["cycles_coarse_mean"], 3),
             "cycles_fine_mean": round(f["cycles_fine_mean"], 3), "cycles_fine_max": f["cycles_fine_max"],
             "status": f["rc"], "flagged_samples": f["flags"], "mean_Y": f["estimate"]["mean_y"],
+            "warm_rejected": f["warm_rejected"],
             "roofline": roofline(f, args.steps),
             "kl_tflops": round(kl_flops / (kl_ms * 1e-3) / 1e12, 2) if kl_n else None,
         }

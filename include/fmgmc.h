@@ -90,6 +90,9 @@ typedef struct {
     int32_t w_max_n;       /* coarse-grid corrections on grids with n <= w_max_n (other than the
                               coarsest) are two cycles in succession (W-cycle); 0 = V-cycles only */
     double rel_tol;        /* stop when ||b - A p||_2 <= rel_tol ||b||_2 at a QoI stage */
+    int32_t inner_first;   /* FP32 V-cycles before the first FP64 refinement of a QoI stage
+                              (FP32_IR; 0 = inner_cycles) */
+    int32_t reserved2;     /* 0 */
 } fmgmc_opts;
 
 typedef struct fmgmc_ctx fmgmc_ctx;

@@ -454,13 +454,13 @@ int prepare(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int level, int t, hipStream
     return FMGMC_OK;
 }
 
-// Cycles of one QoI stage after its first: blocks of G (cycle + check) with one
-// host read per block, until no sample is left or max_cycles is reached.
-int iterate_stage(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int k, int S, int per_cycle, int na,
-                  hipStream_t st,
-                  const std::function<int()> &cycle_and_check) {
+// Cycles of one QoI stage after its first step (first_done cycles): blocks of G
+// steps of per_cycle cycles (+ check) with one host read per block, until no
+// sample is left or max_cycles is reached.
+int iterate_stage(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int k, int S, int first_done, int per_cycle,
+                  int na, hipStream_t st, const std::function<int()> &cycle_and_check) {
     const int G = std::max(1, tn.check_every);
-    int done = per_cycle;
+    int done = first_done;
     while (na > 0 && done < c->opts.max_cycles) {
         const int g = std::min(G, (c->opts.max_cycles - done + per_cycle - 1) / per_cycle);
         const bool graph = tn.graphs && !(c->prof && W.profile);
@@ -502,7 +502,7 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
         TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st));
         TRY(launch_checks(c, W, S, slot, qout, 1, tol, st));
         TRY(read_active(W, st, &na));
-        TRY(iterate_stage(c, W, tn, level, k, S, 1, na, st, [&]() -> int {
+        TRY(iterate_stage(c, W, tn, level, k, S, 1, 1, na, st, [&]() -> int {
             TRY(vcycle<double>(c, W, B, S, k, q, INIT_LOAD, false, OUT_RR | OUT_Q, st));
             return launch_checks(c, W, S, slot, qout, 1, tol, st);
         }));
@@ -601,21 +601,23 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             TRY(launch_copy_f64(W.p64[k], W.p0, int64_t(S) * n * n, st));
         }
         if (warm) TRY(warm_start(c, W, k, S, ia, st, interp));
+        // FP32 cycles before the first FP64 refinement, and per refinement after it
         const int inner = std::max(1, c->opts.inner_cycles);
-        auto step = [&]() -> int {
-            for (int ic = 0; ic < inner; ++ic)
+        const int first = std::min(c->opts.inner_first > 0 ? c->opts.inner_first : inner, c->opts.max_cycles);
+        auto step = [&](int ni) -> int {
+            for (int ic = 0; ic < ni; ++ic)
                 TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st));
             IRArgs iu = ia;
             iu.e = W.x32[k];
             const double irb = double(W.n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
             if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb, st, [&] { return launch_ir(iu, S, st); }));
             else TRY(launch_ir(iu, S, st));
-            return launch_checks(c, W, S, slot, qout, inner, tol, st);
+            return launch_checks(c, W, S, slot, qout, ni, tol, st);
         };
         int na;
-        TRY(step());
+        TRY(step(first));
         TRY(read_active(W, st, &na));
-        TRY(iterate_stage(c, W, tn, level, k, S, inner, na, st, step));
+        TRY(iterate_stage(c, W, tn, level, k, S, first, inner, na, st, [&] { return step(inner); }));
         if (capt) TRY(launch_pack_t(n, S, W.p64[k], W.p0, W.rr0, capt, st));
     }
     return FMGMC_OK;
@@ -788,6 +790,7 @@ int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hi
     c->opts = *opts;
     c->device = device;
     if (c->opts.inner_cycles < 1) c->opts.inner_cycles = 1;
+    if (c->opts.inner_first < 0) c->opts.inner_first = 0;
     int rc = build_mode_table(field->sigma2, field->corr_len, field->n_modes, c->table);
     if (rc != FMGMC_OK) {
         set_error("fmgmc_create: mode table");

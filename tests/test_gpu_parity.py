@@ -318,3 +318,41 @@ def test_hard_high_contrast_sample(solver):
         assert_same_solution(qf, oqf, cyc[:, 1:], ocyc[:, 1:], 1e-10, "  qf")
     else:
         assert np.max(np.abs(qf - oqf) / np.abs(oqf)) < 1e-6
+
+
+@pytest.mark.parametrize("wmax", [32, 16])
+def test_fp64_w_threshold_matches_oracle(wmax):
+    """W-cycle coarse corrections only on grids n <= wmax, both sides."""
+    cfg = CFG2
+    level, S = 3, 6
+    n = cfg["n0"] << level
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=3)
+    log(f"fp64 wmax {wmax} n {n} S {S}")
+    with fmgmc.Context(**cfg, w_max_n=wmax) as ctx:
+        rc, qf, qc, cyc, fl = run_level(ctx, level, xi)
+    oqf, oqc, ocyc, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), n, level, xi, wmax=wmax)
+    assert_same_solution(qf, oqf, cyc[:, 1:], ocyc[:, 1:], 1e-10, "  qf")
+    assert_same_solution(qc, oqc, cyc[:, :1], ocyc[:, :1], 1e-10, "  qc")
+
+
+@pytest.mark.parametrize("first,inner", [(4, 1), (3, 2)])
+def test_ir_cycle_schedule_matches_oracle_to_1e8(first, inner):
+    """FP32 cycles before the first FP64 refinement (first) and per refinement
+    after it (inner), W-cycles on n <= 32: Q within 1e-8 of the oracle at 1e-12."""
+    cfg = CFG2
+    level, S = 3, 6
+    n = cfg["n0"] << level
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=3)
+    log(f"fp32+IR first {first} inner {inner} wmax 32 n {n} S {S}")
+    with fmgmc.Context(**cfg, solver="fp32_ir", rel_tol=1e-12, max_cycles=80, w_max_n=32,
+                       inner_first=first, inner_cycles=inner) as ctx:
+        rc, qf, qc, cyc, fl = run_level(ctx, level, xi)
+    oqf, oqc, _, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), n, level, xi,
+                                   tol=1e-12, max_cycles=80, wmax=32)
+    assert rc == fmgmc.OK and np.all(fl == 0)
+    assert np.all(cyc >= first)
+    assert np.all((cyc - first) % inner == 0)
+    ef = np.abs(qf - oqf) / np.abs(oqf)
+    ec = np.abs(qc - oqc) / np.abs(oqc)
+    log(f"  qf {ef.max():.2e} qc {ec.max():.2e}; cycles {cyc.mean(axis=0)}")
+    assert ef.max() <= 1e-8 and ec.max() <= 1e-8
