@@ -463,7 +463,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=4096)
-    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--inner", type=int, default=1)
     ap.add_argument("--inner-first", type=int, default=4, help="FP32 cycles before the first refinement")
     ap.add_argument("--wmax", type=int, default=32, help="W-cycle coarse corrections on grids n <= wmax")
