@@ -536,6 +536,7 @@ def main():
             "warm_rejected": f["warm_rejected"],
             "roofline": roofline(f, args.steps),
             "kl_tflops": round(kl_flops / (kl_ms * 1e-3) / 1e12, 2) if kl_n else None,
+            "kl_ms_per_step": round(kl_ms / args.steps, 3) if kl_n else None,
         }
         cnn_ms, cnn_n, cnn_flops = f["prof"]["cnn"]
         if cnn_n:

@@ -58,7 +58,13 @@ enum {
 
 enum { FMGMC_COV_SEPARABLE_EXP = 0 };
 enum { FMGMC_SOLVER_FP64 = 0, FMGMC_SOLVER_FP32_IR = 1 };
-enum { FMGMC_KL_FP64 = 0, FMGMC_KL_FP32 = 1, FMGMC_KL_BF16 = 2 };
+/* KL synthesis arithmetic. FP64: the separable factorisation (two FP64 MFMA
+ * contractions through the per-sample 1-D coefficient matrix) on grids n >= 64
+ * with at most 64 1-D modes per axis, else the dense contraction. FP32, BF16:
+ * the dense samples x modes x cells contraction with FP32 accumulation.
+ * FP64_DENSE: the dense contraction in FP64. All forms compute the same sum
+ * (Section 3.1 (2)) up to rounding. */
+enum { FMGMC_KL_FP64 = 0, FMGMC_KL_FP32 = 1, FMGMC_KL_BF16 = 2, FMGMC_KL_FP64_DENSE = 3 };
 
 /* Random field (Section 3.1 (2)). */
 typedef struct {
@@ -218,7 +224,9 @@ int fmgmc_kl_modes(double sigma2, double corr_len, int32_t n_modes, int32_t *a, 
  * KL contraction) is accumulated from the number of samples still iterating.
  * Kinds: 0 pre-smoothing + residual + restriction pass, 1 prolongation +
  * post-smoothing pass (+ residual norm, QoI), 2 FP64 refinement pass,
- * 3 KL synthesis, 4 coarse-grid V-cycle in LDS, 5 warm-start network
+ * 3 KL synthesis (flops of the path taken: 2 M n^2 per sample for the dense
+ * contraction, 2 A n (A + n) for the separable one with A 1-D modes per
+ * axis), 4 coarse-grid V-cycle in LDS, 5 warm-start network
  * inference (flops; all its layers, every QoI stage it runs on).
  * fmgmc_profile_read synchronises, returns the summed kernel time in ms,
  * the launch count and the algorithmic bytes (flops for kind 3), and clears

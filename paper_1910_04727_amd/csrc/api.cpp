@@ -633,7 +633,7 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
     const int nf = h->n0 << (h->n_levels - 1);
     if (nf > 1024) return FMGMC_EINVAL;
     if (o->solver != FMGMC_SOLVER_FP64 && o->solver != FMGMC_SOLVER_FP32_IR) return FMGMC_EINVAL;
-    if (o->kl_prec < FMGMC_KL_FP64 || o->kl_prec > FMGMC_KL_BF16) return FMGMC_EINVAL;
+    if (o->kl_prec < FMGMC_KL_FP64 || o->kl_prec > FMGMC_KL_FP64_DENSE) return FMGMC_EINVAL;
     // smoothing sweeps: 1..2 in FP64 cycles, 1..4 in FP32 cycles
     const int nu_max = o->solver == FMGMC_SOLVER_FP32_IR ? 4 : 2;
     if (o->nu1 < 1 || o->nu1 > nu_max || o->nu2 < 1 || o->nu2 > nu_max || o->max_cycles < 1 || !(o->rel_tol > 0))
@@ -684,6 +684,7 @@ int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n
         a.M = M;
         a.xi = x;
         a.phi = ctx->d_phi[level];
+        a.kdim = ctx->table.kmax + 1;
         a.ma = ctx->d_ma;
         a.mb = ctx->d_mb;
         a.sqrtlam = ctx->d_sqrtlam;
@@ -700,7 +701,7 @@ int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n
             W.cap_x[sl] = W.capx_base[sl] ? W.capx_base[sl] + size_t(s0) * 2 * ns * ns : nullptr;
             W.cap_t[sl] = W.capt_base[sl] ? W.capt_base[sl] + size_t(s0) * ns * ns : nullptr;
         }
-        const double klf = 2.0 * double(M) * double(n) * n * S;
+        const double klf = kl_flops(a, ctx->opts.kl_prec) * S;
         TRY(timed(ctx, W, FMGMC_PROF_KL, klf, st, [&] { return launch_kl(a, S, ctx->opts.kl_prec, st); }));
         TRY(ir ? run_batch_ir(ctx, W, tn, level, S, qf, qc, st) : run_batch_fp64(ctx, W, tn, level, S, qf, qc, st));
         FMGMC_HIP(hipMemcpyAsync(q_fine + s0, qf, S * sizeof(double),
@@ -921,6 +922,7 @@ int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, con
         a.M = M;
         a.xi = x;
         a.phi = ctx->d_phi[level];
+        a.kdim = ctx->table.kmax + 1;
         a.ma = ctx->d_ma;
         a.mb = ctx->d_mb;
         a.sqrtlam = ctx->d_sqrtlam;

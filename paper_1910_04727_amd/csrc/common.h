@@ -105,7 +105,8 @@ struct KLArgs {
     int n;                // finest grid of the level
     int M;
     const double *xi;     // [S][M]
-    const double *phi;    // [kmax+1][n] 1-D eigenfunctions on the grid points
+    const double *phi;    // [kdim][n] 1-D eigenfunctions on the grid points
+    int kdim;             // 1-D modes per axis in use (kmax + 1)
     const int32_t *ma, *mb;
     const double *sqrtlam;// [M]
     int nlev;             // pyramid levels written (finest first): n, n/2, ...
@@ -113,6 +114,9 @@ struct KLArgs {
     float *K32[9];        // nullable per level
 };
 int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st);
+// whether launch_kl takes the separable path, and its flops per sample
+bool kl_separable(const KLArgs &a, int prec);
+double kl_flops(const KLArgs &a, int prec);
 
 // FP64 refinement: p += e (optional), r = b - A p (FP64, K64 stage operator),
 // r -> r32 (rhs of the next inner cycles), rr, Q.

@@ -191,6 +191,90 @@ __global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
             store_pyramid(A, S, s0 + 16 * w + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), double(acc[q][v]), true);
 }
 
+// ---------------------------------------------------------------- separable
+// For the separable covariance every 2-D mode is a product of 1-D modes
+// (Section 3.1 (2)), so the same sum factors through a small per-sample matrix:
+//   g_s(x_i, y_j) = sum_a phi_a(x_i) T_s[a][j],   T_s[a][j] = sum_b C_s[a][b] phi_b(y_j),
+//   C_s[a_m][b_m] = xi_s[m] sqrt(lambda_m), zero for pairs that are not kept modes.
+// With A 1-D modes per axis (A <= 64) this is 2 (A + n) A n flops per sample
+// instead of 2 M n^2, and the pass is bound by writing the coefficient pyramid.
+// Workgroup: one sample and a band of 64 grid rows; T for the band is formed
+// once (FP64 MFMA), then each 64-cell x-tile of the band is one FP64 MFMA
+// contraction over a. LDS strides keep the operand reads conflict-free
+// (A-type reads: stride = 2 mod 4 doubles per pair of rows; T: 80).
+constexpr int SB = 64;
+constexpr int TSTR = SB + 16;
+
+template <int AP>
+__global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
+    constexpr int CSd = AP + 2;
+    extern __shared__ double sm[];
+    double *Cm = sm;                 // [AP][CSd]   C_s[a][b]
+    double *P = Cm + AP * CSd;       // [SB][CSd]   phi_b(y_j) of the band, then phi_a(x_i) of an x-tile
+    double *Tt = P + SB * CSd;       // [AP][TSTR]  T_s[a][j] of the band
+    const int n = A.n, s = blockIdx.y, j0 = blockIdx.x * SB, KD = A.kdim;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    if (s >= S) return;
+    for (int e = t; e < AP * CSd; e += 256) Cm[e] = 0.0;
+    for (int e = t; e < SB * CSd; e += 256) {
+        const int jj = e / CSd, b = e % CSd;
+        P[e] = (b < KD) ? A.phi[size_t(b) * n + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+    for (int m = t; m < A.M; m += 256) Cm[A.ma[m] * CSd + A.mb[m]] = A.xi[size_t(s) * A.M + m] * A.sqrtlam[m];
+    __syncthreads();
+    {   // T[a][j] = sum_b C[a][b] phi_b(y_j): wave w owns the j columns 16w .. 16w+15
+        d4 acc[AP / 16];
+#pragma unroll
+        for (int q = 0; q < AP / 16; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int kk = 0; kk < AP / 4; ++kk) {
+            const double bv = P[(16 * w + (l & 15)) * CSd + 4 * kk + (l >> 4)];
+#pragma unroll
+            for (int q = 0; q < AP / 16; ++q) {
+                const double av = Cm[(16 * q + (l & 15)) * CSd + 4 * kk + (l >> 4)];
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < AP / 16; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Tt[(16 * q + 4 * v + (l >> 4)) * TSTR + 16 * w + (l & 15)] = acc[q][v];
+    }
+    for (int i0 = 0; i0 < n; i0 += SB) {
+        __syncthreads();  // T complete / previous tile's reads of P done
+        for (int e = t; e < SB * CSd; e += 256) {
+            const int ii = e / CSd, a = e % CSd;
+            P[e] = (a < KD) ? A.phi[size_t(a) * n + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+        // g[j][i] = sum_a T[a][j] phi_a(x_i): wave w owns rows j 16w .., four 16-cell i-tiles
+        d4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int kk = 0; kk < AP / 4; ++kk) {
+            const double av = Tt[(4 * kk + (l >> 4)) * TSTR + 16 * w + (l & 15)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double bv = P[(16 * q + (l & 15)) * CSd + 4 * kk + (l >> 4)];
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                store_pyramid(A, S, s, (j0 + 16 * w + 4 * v + (l >> 4)) * n + i0 + 16 * q + (l & 15), acc[q][v],
+                              false);
+    }
+}
+
+template <int AP>
+size_t sep_lds() {
+    return size_t(AP * (AP + 2) + SB * (AP + 2) + AP * TSTR) * sizeof(double);
+}
+
 // BF16 inputs, FP32 accumulation: v_mfma_f32_16x16x32_bf16. Lane l holds
 // A[row l%16][k = 8 (l/16) .. +7] and B[k = 8 (l/16) .. +7][col l%16]; D as above.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -242,11 +326,29 @@ __global__ __launch_bounds__(256) void k_kl_bf16(KLArgs A, int S) {
 
 }  // namespace
 
+bool kl_separable(const KLArgs &a, int prec) {
+    return prec == FMGMC_KL_FP64 && a.n >= SB && a.n % SB == 0 && a.kdim >= 1 && a.kdim <= 64;
+}
+
+double kl_flops(const KLArgs &a, int prec) {
+    const double n = a.n, kd = a.kdim;
+    return kl_separable(a, prec) ? 2.0 * kd * n * (kd + n) : 2.0 * double(a.M) * n * n;
+}
+
 int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st) {
     if (S <= 0) return FMGMC_OK;
+    if (kl_separable(a, prec)) {
+        const dim3 g(a.n / SB, S), b(256);
+        const int ap = (a.kdim + 15) / 16 * 16;
+        if (ap == 16) hipLaunchKernelGGL(k_kl_sep_f64<16>, g, b, sep_lds<16>(), st, a, S);
+        else if (ap == 32) hipLaunchKernelGGL(k_kl_sep_f64<32>, g, b, sep_lds<32>(), st, a, S);
+        else if (ap == 48) hipLaunchKernelGGL(k_kl_sep_f64<48>, g, b, sep_lds<48>(), st, a, S);
+        else hipLaunchKernelGGL(k_kl_sep_f64<64>, g, b, sep_lds<64>(), st, a, S);
+        return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+    }
     dim3 grid((a.n * a.n + TC - 1) / TC, (S + TS - 1) / TS), block(256);
     const size_t dyn = size_t(a.M) * (sizeof(double) + sizeof(int));
-    if (prec == FMGMC_KL_FP64) hipLaunchKernelGGL(k_kl_f64, grid, block, dyn, st, a, S);
+    if (prec == FMGMC_KL_FP64 || prec == FMGMC_KL_FP64_DENSE) hipLaunchKernelGGL(k_kl_f64, grid, block, dyn, st, a, S);
     else if (prec == FMGMC_KL_FP32) hipLaunchKernelGGL(k_kl_f32, grid, block, dyn, st, a, S);
     else if (prec == FMGMC_KL_BF16) hipLaunchKernelGGL(k_kl_bf16, grid, block, 0, st, a, S);
     else {

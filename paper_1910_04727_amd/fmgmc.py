@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libfmgmc.so")
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
 FLAG_NOTCONV, FLAG_NONFINITE = 1, 2
 SOLVERS = {"fp64": 0, "fp32_ir": 1}
-KL_PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+KL_PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp64_dense": 3}
 
 
 class Field(C.Structure):

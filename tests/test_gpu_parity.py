@@ -67,14 +67,16 @@ def assert_same_solution(g, o, gcyc, ocyc, rel_tol, label):
 
 
 # ------------------------------------------------------------------ KL field
-@pytest.mark.parametrize("level,S", [(0, 70), (1, 33), (3, 70)])
-def test_field_fp64_matches_oracle(level, S):
-    """32^2 and 64^2 (narrow tiles) and 256^2 (wide row tiles), ragged sample counts."""
+@pytest.mark.parametrize("level,S,prec", [(0, 70, "fp64"), (1, 33, "fp64"), (3, 70, "fp64"), (1, 9, "fp64_dense"),
+                                          (3, 5, "fp64_dense")])
+def test_field_fp64_matches_oracle(level, S, prec):
+    """FP64: 32^2 (dense contraction, narrow tiles), 64^2 and 256^2 (separable factorisation);
+    FP64_DENSE: the dense contraction at 64^2 and 256^2 (row-staged tiles). Ragged sample counts."""
     cfg = CFG2
     n = cfg["n0"] << level
     xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=1)
-    log(f"field fp64 level {level} n {n} S {S}")
-    with fmgmc.Context(**cfg) as ctx:
+    log(f"field {prec} level {level} n {n} S {S}")
+    with fmgmc.Context(**cfg, kl_prec=prec) as ctx:
         K = torch.zeros((S, n, n), dtype=torch.float64, device="cuda")
         ctx.synthesize_field(level, dev(xi), K)
         torch.cuda.synchronize()
@@ -356,3 +358,22 @@ def test_ir_cycle_schedule_matches_oracle_to_1e8(first, inner):
     ec = np.abs(qc - oqc) / np.abs(oqc)
     log(f"  qf {ef.max():.2e} qc {ec.max():.2e}; cycles {cyc.mean(axis=0)}")
     assert ef.max() <= 1e-8 and ec.max() <= 1e-8
+
+
+def test_field_separable_at_many_modes():
+    """1024 modes at correlation length 0.05 (60 1-D modes per axis, the 64-wide
+    factorisation) at 128^2 against the oracle."""
+    cfg = dict(sigma2=3.0, corr_len=0.05, n_modes=1024, n_levels=6, n0=32)
+    level, S = 2, 3
+    n = cfg["n0"] << level
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=4, level=level, purpose=1)
+    with fmgmc.Context(**cfg) as ctx:
+        K = torch.zeros((S, n, n), dtype=torch.float64, device="cuda")
+        ctx.synthesize_field(level, dev(xi), K)
+        torch.cuda.synchronize()
+        K = K.cpu().numpy()
+    tab = table(cfg)
+    worst = max(float(np.max(np.abs(K[s] - O.field(n, cfg["corr_len"], tab, xi[s])) /
+                         O.field(n, cfg["corr_len"], tab, xi[s]))) for s in range(S))
+    log(f"separable 1024 modes n {n}: max rel err {worst:.2e}")
+    assert worst <= 1e-12
