@@ -98,7 +98,9 @@ typedef struct {
     double rel_tol;        /* stop when ||b - A p||_2 <= rel_tol ||b||_2 at a QoI stage */
     int32_t inner_first;   /* FP32 V-cycles before the first FP64 refinement of a QoI stage
                               (FP32_IR; 0 = inner_cycles) */
-    int32_t reserved2;     /* 0 */
+    int32_t separate_coarse; /* 0: Q^c_l from the FMG pass that yields Q^f_l (FMG-MLMC,
+                                Section 2.5); 1: Q^c_l from a separate FMG solve on n_l/2, as in
+                                standard MLMC (the comparator of the paper's saving) */
 } fmgmc_opts;
 
 typedef struct fmgmc_ctx fmgmc_ctx;

@@ -474,40 +474,58 @@ int iterate_stage(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int k, int S
     return FMGMC_OK;
 }
 
+// FMG-MLMC (default): one pass whose stages n_l/2 and n_l both run to the
+// tolerance, giving Q^c_l and Q^f_l (Section 2.5, Algorithm 3). With
+// separate_coarse (the standard-MLMC comparator, levels >= 1): Q^c_l from its own
+// FMG pass ending at n_l/2, then a pass to n_l in which n_l/2 is an ordinary
+// intermediate stage (one cycle). Both passes use the injected coefficients.
+template <typename P>
+int run_passes(fmgmc_ctx *c, int level, int t, double *qf, double *qc, P &&pass) {
+    if (level >= 1 && c->opts.separate_coarse) {
+        TRY(pass(t - 1, false, qc, 0));
+        return pass(t, false, qf, 1);
+    }
+    return pass(t, level >= 1, qf, 1);
+}
+
 int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double *qf, double *qc,
                    hipStream_t st) {
     const int t = ilog2((c->hier.n0 << level) / W.nsz[0]);
     Bufs<double> B = bufs64(W);
     TRY(prepare<double>(c, W, B, S, level, t, st));
     const double tol = c->opts.rel_tol;
-    for (int k = 0; k <= t; ++k) {
-        const bool fine = (k == t), coarse = (level >= 1 && k == t - 1);
-        const int q = (level >= 1 && k <= t - 1) ? 0 : 1;
-        TRY(launch_fill_i32(W.active, 1, S, st));
-        W.n_active_host = S;
-        if (!(fine || coarse)) {
-            TRY(vcycle<double>(c, W, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
-            continue;
-        }
-        double *qout = fine ? qf : qc;
-        const int slot = fine ? 1 : 0;
-        TRY(launch_bnorm<double>(W.nsz[k], B.K[k], c->hier.p_west, c->hier.p_east, W.bnorm, S, st));
-        int na;
-        if (k == 0) {  // direct solve: exact, no cycles
-            TRY(vcycle<double>(c, W, B, S, 0, q, INIT_ZERO, false, OUT_RR | OUT_Q, st));
-            TRY(launch_checks(c, W, S, slot, qout, 0, INFINITY, st));
+    // one FMG pass up to stage ktop; with_coarse: stage ktop - 1 is a QoI stage too
+    auto pass = [&](int ktop, bool with_coarse, double *qtop, int slot_top) -> int {
+        for (int k = 0; k <= ktop; ++k) {
+            const bool fine = (k == ktop), coarse = (with_coarse && k == ktop - 1);
+            const int q = (level >= 1 && k <= t - 1) ? 0 : 1;
+            TRY(launch_fill_i32(W.active, 1, S, st));
+            W.n_active_host = S;
+            if (!(fine || coarse)) {
+                TRY(vcycle<double>(c, W, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
+                continue;
+            }
+            double *qout = fine ? qtop : qc;
+            const int slot = fine ? slot_top : 0;
+            TRY(launch_bnorm<double>(W.nsz[k], B.K[k], c->hier.p_west, c->hier.p_east, W.bnorm, S, st));
+            int na;
+            if (k == 0) {  // direct solve: exact, no cycles
+                TRY(vcycle<double>(c, W, B, S, 0, q, INIT_ZERO, false, OUT_RR | OUT_Q, st));
+                TRY(launch_checks(c, W, S, slot, qout, 0, INFINITY, st));
+                TRY(read_active(W, st, &na));
+                continue;
+            }
+            TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st));
+            TRY(launch_checks(c, W, S, slot, qout, 1, tol, st));
             TRY(read_active(W, st, &na));
-            continue;
+            TRY(iterate_stage(c, W, tn, level, k, S, 1, 1, na, st, [&]() -> int {
+                TRY(vcycle<double>(c, W, B, S, k, q, INIT_LOAD, false, OUT_RR | OUT_Q, st));
+                return launch_checks(c, W, S, slot, qout, 1, tol, st);
+            }));
         }
-        TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st));
-        TRY(launch_checks(c, W, S, slot, qout, 1, tol, st));
-        TRY(read_active(W, st, &na));
-        TRY(iterate_stage(c, W, tn, level, k, S, 1, 1, na, st, [&]() -> int {
-            TRY(vcycle<double>(c, W, B, S, k, q, INIT_LOAD, false, OUT_RR | OUT_Q, st));
-            return launch_checks(c, W, S, slot, qout, 1, tol, st);
-        }));
-    }
-    return FMGMC_OK;
+        return FMGMC_OK;
+    };
+    return run_passes(c, level, t, qf, qc, pass);
 }
 
 // Learned warm start of one QoI stage (p64 holds the FMG start p~, rr its
@@ -557,70 +575,74 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
     TRY(prepare<float>(c, W, B, S, level, t, st));
     const double tol = c->opts.rel_tol;
     const double pW = c->hier.p_west, pE = c->hier.p_east;
-    for (int k = 0; k <= t; ++k) {
-        const bool fine = (k == t), coarse = (level >= 1 && k == t - 1);
-        const int q = (level >= 1 && k <= t - 1) ? 0 : 1;
-        TRY(launch_fill_i32(W.active, 1, S, st));
-        W.n_active_host = S;
-        if (!(fine || coarse)) {
-            TRY(vcycle<float>(c, W, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
-            continue;
+    // one FMG pass up to stage ktop; with_coarse: stage ktop - 1 is a QoI stage too
+    auto pass = [&](int ktop, bool with_coarse, double *qtop, int slot_top) -> int {
+        for (int k = 0; k <= ktop; ++k) {
+            const bool fine = (k == ktop), coarse = (with_coarse && k == ktop - 1);
+            const int q = (level >= 1 && k <= t - 1) ? 0 : 1;
+            TRY(launch_fill_i32(W.active, 1, S, st));
+            W.n_active_host = S;
+            if (!(fine || coarse)) {
+                TRY(vcycle<float>(c, W, B, S, k, q, k == 0 ? INIT_ZERO : INIT_INTERP, false, 0, st));
+                continue;
+            }
+            double *qout = fine ? qtop : qc;
+            const int slot = fine ? slot_top : 0;
+            const int n = W.nsz[k];
+            // FMG start in FP64: from the FP64 solution when the stage below was a QoI stage
+            auto interp = [&]() -> int {
+                if (fine && with_coarse) return launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, pW, pE, S, st);
+                return launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, pW, pE, S, st);
+            };
+            TRY(interp());
+            TRY(launch_bnorm<double>(n, W.K64[k], pW, pE, W.bnorm, S, st));
+            IRArgs ia{};
+            ia.n = n;
+            ia.p = W.p64[k];
+            ia.e = nullptr;
+            ia.K = W.K64[k];
+            ia.r32 = W.b32[k];
+            ia.rr = W.rr;
+            ia.q = W.q;
+            ia.active = W.active;
+            ia.pW = pW;
+            ia.pE = pE;
+            {
+                // first residual of the stage: reads p and K, writes r (20 B per cell)
+                const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
+                if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
+                else TRY(launch_ir(ia, S, st));
+            }
+            const bool warm = c->warm && n >= c->warm_min_n;
+            float *capx = W.cap_x[slot], *capt = W.cap_t[slot];
+            if (warm || capx) TRY(launch_copy_f64(W.rr, W.rr0, S, st));
+            if (capx) {
+                TRY(launch_pack_x(n, S, W.K32[k], W.b32[k], W.rr0, capx, st));
+                TRY(launch_copy_f64(W.p64[k], W.p0, int64_t(S) * n * n, st));
+            }
+            if (warm) TRY(warm_start(c, W, k, S, ia, st, interp));
+            // FP32 cycles before the first FP64 refinement, and per refinement after it
+            const int inner = std::max(1, c->opts.inner_cycles);
+            const int first = std::min(c->opts.inner_first > 0 ? c->opts.inner_first : inner, c->opts.max_cycles);
+            auto step = [&](int ni) -> int {
+                for (int ic = 0; ic < ni; ++ic)
+                    TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st));
+                IRArgs iu = ia;
+                iu.e = W.x32[k];
+                const double irb = double(W.n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
+                if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb, st, [&] { return launch_ir(iu, S, st); }));
+                else TRY(launch_ir(iu, S, st));
+                return launch_checks(c, W, S, slot, qout, ni, tol, st);
+            };
+            int na;
+            TRY(step(first));
+            TRY(read_active(W, st, &na));
+            TRY(iterate_stage(c, W, tn, level, k, S, first, inner, na, st, [&] { return step(inner); }));
+            if (capt) TRY(launch_pack_t(n, S, W.p64[k], W.p0, W.rr0, capt, st));
         }
-        double *qout = fine ? qf : qc;
-        const int slot = fine ? 1 : 0;
-        const int n = W.nsz[k];
-        // FMG start in FP64
-        auto interp = [&]() -> int {
-            if (fine && level >= 1) return launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, pW, pE, S, st);
-            return launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, pW, pE, S, st);
-        };
-        TRY(interp());
-        TRY(launch_bnorm<double>(n, W.K64[k], pW, pE, W.bnorm, S, st));
-        IRArgs ia{};
-        ia.n = n;
-        ia.p = W.p64[k];
-        ia.e = nullptr;
-        ia.K = W.K64[k];
-        ia.r32 = W.b32[k];
-        ia.rr = W.rr;
-        ia.q = W.q;
-        ia.active = W.active;
-        ia.pW = pW;
-        ia.pE = pE;
-        {
-            // first residual of the stage: reads p and K, writes r (20 B per cell)
-            const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
-            if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
-            else TRY(launch_ir(ia, S, st));
-        }
-        const bool warm = c->warm && n >= c->warm_min_n;
-        float *capx = W.cap_x[slot], *capt = W.cap_t[slot];
-        if (warm || capx) TRY(launch_copy_f64(W.rr, W.rr0, S, st));
-        if (capx) {
-            TRY(launch_pack_x(n, S, W.K32[k], W.b32[k], W.rr0, capx, st));
-            TRY(launch_copy_f64(W.p64[k], W.p0, int64_t(S) * n * n, st));
-        }
-        if (warm) TRY(warm_start(c, W, k, S, ia, st, interp));
-        // FP32 cycles before the first FP64 refinement, and per refinement after it
-        const int inner = std::max(1, c->opts.inner_cycles);
-        const int first = std::min(c->opts.inner_first > 0 ? c->opts.inner_first : inner, c->opts.max_cycles);
-        auto step = [&](int ni) -> int {
-            for (int ic = 0; ic < ni; ++ic)
-                TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st));
-            IRArgs iu = ia;
-            iu.e = W.x32[k];
-            const double irb = double(W.n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
-            if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb, st, [&] { return launch_ir(iu, S, st); }));
-            else TRY(launch_ir(iu, S, st));
-            return launch_checks(c, W, S, slot, qout, ni, tol, st);
-        };
-        int na;
-        TRY(step(first));
-        TRY(read_active(W, st, &na));
-        TRY(iterate_stage(c, W, tn, level, k, S, first, inner, na, st, [&] { return step(inner); }));
-        if (capt) TRY(launch_pack_t(n, S, W.p64[k], W.p0, W.rr0, capt, st));
-    }
-    return FMGMC_OK;
+        return FMGMC_OK;
+    };
+    return run_passes(c, level, t, qf, qc, pass);
 }
 
 int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
@@ -639,7 +661,7 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
     if (o->nu1 < 1 || o->nu1 > nu_max || o->nu2 < 1 || o->nu2 > nu_max || o->max_cycles < 1 || !(o->rel_tol > 0))
         return FMGMC_EINVAL;
     if (o->solver == FMGMC_SOLVER_FP32_IR && h->n0 < 8) return FMGMC_EINVAL;  // QoI stages need n >= 8
-    if (o->max_batch < 0 || o->w_max_n < 0) return FMGMC_EINVAL;
+    if (o->max_batch < 0 || o->w_max_n < 0 || o->separate_coarse < 0 || o->separate_coarse > 1) return FMGMC_EINVAL;
     return FMGMC_OK;
 }
 

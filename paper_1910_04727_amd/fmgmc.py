@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("kl_prec", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("inner_cycles", C.c_int32),
                 ("max_batch", C.c_int32), ("w_max_n", C.c_int32), ("rel_tol", C.c_double),
-                ("inner_first", C.c_int32), ("reserved2", C.c_int32)]
+                ("inner_first", C.c_int32), ("separate_coarse", C.c_int32)]
 
 
 class LevelEst(C.Structure):
@@ -141,11 +141,11 @@ class Context:
 
     def __init__(self, sigma2, corr_len, n_modes, n_levels, n0, solver="fp64", kl_prec="fp64",
                  nu1=2, nu2=2, max_cycles=50, inner_cycles=1, max_batch=0, rel_tol=1e-10,
-                 p_west=1.0, p_east=0.0, device=0, w_max_n=64, inner_first=0):
+                 p_west=1.0, p_east=0.0, device=0, w_max_n=64, inner_first=0, separate_coarse=False):
         self.field = Field(sigma2, corr_len, n_modes, 0)
         self.hier = Hier(n_levels, n0, 4, 0, p_west, p_east)
         self.opts = Opts(SOLVERS[solver], KL_PREC[kl_prec], nu1, nu2, max_cycles, inner_cycles,
-                         max_batch, w_max_n, rel_tol, inner_first, 0)
+                         max_batch, w_max_n, rel_tol, inner_first, 1 if separate_coarse else 0)
         self.n_modes = n_modes
         self.n0 = n0
         self.n_levels = n_levels

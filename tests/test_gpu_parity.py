@@ -377,3 +377,26 @@ def test_field_separable_at_many_modes():
                          O.field(n, cfg["corr_len"], tab, xi[s]))) for s in range(S))
     log(f"separable 1024 modes n {n}: max rel err {worst:.2e}")
     assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("solver,bound", [("fp64", 1e-10), ("fp32_ir", 1e-8)])
+def test_separate_coarse_solve_is_standard_mlmc(solver, bound):
+    """Standard-MLMC comparator: Q^c_l from its own FMG solve on n_l/2, which is
+    the oracle's level l-1 solve of the same (injected) field; Q^f_l from a pass
+    in which n_l/2 is an intermediate stage, against the oracle's Q^f_l."""
+    cfg = CFG2
+    level, S = 3, 6
+    n = cfg["n0"] << level
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=3)
+    log(f"separate coarse solve, {solver}, n {n}")
+    with fmgmc.Context(**cfg, solver=solver, separate_coarse=True, rel_tol=1e-12, max_cycles=80) as ctx:
+        rc, qf, qc, cyc, fl = run_level(ctx, level, xi)
+    assert rc == fmgmc.OK and np.all(fl == 0)
+    oc, _, ocyc_c, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), n // 2, level - 1, xi,
+                                     tol=1e-12, max_cycles=80)
+    of, _, _, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), n, level, xi, tol=1e-12, max_cycles=80)
+    ec = np.abs(qc - oc) / np.abs(oc)
+    ef = np.abs(qf - of) / np.abs(of)
+    log(f"  qc vs oracle level {level - 1}: {ec.max():.2e} (cycles {cyc[:, 0].mean():.2f} vs {ocyc_c[:, 1].mean():.2f}); "
+        f"qf {ef.max():.2e}")
+    assert ec.max() <= bound and ef.max() <= 1e-8
