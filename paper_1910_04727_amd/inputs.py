@@ -82,15 +82,31 @@ def sobol_ints(M, m_log2, config, level, seed=SEED):
     return np.round(u * float(1 << _BITS)).astype(np.uint64)
 
 
-def rqmc_normals(M, m_log2, nshift, config, level, seed=SEED):
-    """[nshift * 2^m_log2, M] standard normals, grouped shift-major."""
-    from scipy.special import ndtri
-    base = sobol_ints(M, m_log2, config, level, seed)
+def _shifts(M, nshift, config, level, seed):
     ss = np.random.SeedSequence([seed, config, level, 8])
     g = np.random.Generator(np.random.PCG64(ss))
-    shifts = g.integers(0, 1 << _BITS, size=(nshift, M), dtype=np.uint64)
-    out = np.empty((nshift, base.shape[0], M))
-    for r in range(nshift):
+    return g.integers(0, 1 << _BITS, size=(nshift, M), dtype=np.uint64)
+
+
+def _shifted_normals(base, shifts):
+    from scipy.special import ndtri
+    out = np.empty((shifts.shape[0], base.shape[0], base.shape[1]))
+    for r in range(shifts.shape[0]):
         k = np.bitwise_xor(base, shifts[r][None, :])
         out[r] = ndtri((k.astype(np.float64) + 0.5) * (1.0 / float(1 << _BITS)))
-    return out.reshape(nshift * base.shape[0], M)
+    return out
+
+
+def rqmc_normals(M, m_log2, nshift, config, level, seed=SEED):
+    """[nshift * 2^m_log2, M] standard normals, grouped shift-major."""
+    base = sobol_ints(M, m_log2, config, level, seed)
+    return _shifted_normals(base, _shifts(M, nshift, config, level, seed)).reshape(nshift * base.shape[0], M)
+
+
+def rqmc_normals_range(M, m_from, m_to, nshift, config, level, seed=SEED):
+    """Points 2^m_from .. 2^m_to - 1 of the same scrambled Sobol' sequence and
+    shifts as rqmc_normals (all points if m_from < 0): [nshift, count, M], so a
+    point set can be doubled without recomputing the points it already has."""
+    base = sobol_ints(M, m_to, config, level, seed)
+    lo = 0 if m_from < 0 else (1 << m_from)
+    return _shifted_normals(base[lo:], _shifts(M, nshift, config, level, seed))
