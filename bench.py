@@ -275,7 +275,8 @@ def report_cfg2(torch, fmgmc, inputs, args):
 
 
 def report_cfg3(torch, fmgmc, inputs, args):
-    """RQMC (Sobol' 2^14 x 16 shifts) against MC (2^18 i.i.d.) per level; KL in FP64 / FP32 / BF16."""
+    """RQMC (Sobol' 2^14 x 16 digital shifts; the embedded lattice sequence's first 2^14 points x 16
+    random shifts) against MC (2^18 i.i.d.) per level; KL in FP64 / FP32 / BF16 on the Sobol' points."""
     cfg = dict(sigma2=2.0, corr_len=0.1, n_modes=512, n_levels=4, n0=64)
     m_log2, R = 14, 16
     N = R << m_log2
@@ -283,7 +284,7 @@ def report_cfg3(torch, fmgmc, inputs, args):
     ctxs = {k: fmgmc.Context(**cfg, solver="fp32_ir", kl_prec=p, max_batch=2048, max_cycles=60)
             for k, p in forms.items()}
     lv = []
-    tot = dict(var_rqmc=0.0, var_mc=0.0, est_rqmc=0.0, est_mc=0.0, seconds=0.0)
+    tot = dict(var_rqmc=0.0, var_lattice=0.0, var_mc=0.0, est_rqmc=0.0, est_lattice=0.0, est_mc=0.0, seconds=0.0)
     kl_est = {k: 0.0 for k in forms}
     for l in range(cfg["n_levels"]):
         xq_host = inputs.rqmc_normals(cfg["n_modes"], m_log2, R, config=3, level=l)
@@ -311,6 +312,15 @@ def report_cfg3(torch, fmgmc, inputs, args):
             m = b != 0
             row[f"{k}_qoi_rel_err"] = _rel(a[m], b[m])
         del xq, q
+        xl = _dev(torch, inputs.lattice_normals_range(cfg["n_modes"], -1, m_log2, R, config=3, level=l).reshape(N, -1))
+        qf, qc, c, fl = _bufs(torch, N)
+        ctxs["kl_fp64"].solve_level(l, xl, qf, qc, c, fl)
+        e = fmgmc.estimate([qf], [qc], n_shifts=R)
+        row.update(lattice_mean=e["mean"], lattice_var_of_mean=e["var_of_mean"],
+                   variance_ratio_lattice_over_sobol=e["var_of_mean"] / row["rqmc_var_of_mean"])
+        tot["est_lattice"] += e["mean"]
+        tot["var_lattice"] += e["var_of_mean"]
+        del xl
         xm = _dev(torch, inputs.mc_normals_blocked(0, N, cfg["n_modes"], config=3, level=l))
         qf, qc, c, fl = _bufs(torch, N)
         ctxs["kl_fp64"].solve_level(l, xm, qf, qc, c, fl)
@@ -333,9 +343,9 @@ def report_cfg3(torch, fmgmc, inputs, args):
         c.close()
     return {"metric": "cfg3 MLQMC vs MLMC estimator variance at equal cost", "value":
             round(tot["var_mc"] / tot["var_rqmc"], 3), "unit": "variance ratio MC/RQMC (total)",
-            "levels": lv, "total": tot, "kl_precision_estimates": kl_est,
+            "variance_ratio_mc_over_lattice": round(tot["var_mc"] / tot["var_lattice"], 3), "levels": lv, "total": tot, "kl_precision_estimates": kl_est,
             "config": {"workload": "4 levels 64^2..512^2, sigma2=2, corr_len=0.1, 512 KL modes, 2^14 Sobol' "
-                                   "points x 16 digital shifts per level vs 2^18 i.i.d.; FP32+IR to 1e-10; "
+                                   "points x 16 digital shifts and 2^14 lattice points x 16 random shifts per level vs 2^18 i.i.d.; FP32+IR to 1e-10; "
                                    "KL contraction in FP64, FP32 and BF16"}}
 
 

@@ -10,8 +10,9 @@ batched level solves.
     samples, and when none are needed test the weak error by Richardson
     extrapolation, |mean Y_L| / (2^alpha - 1) < eps / sqrt(2); add a level if
     it fails.
-  - mlqmc: the MLQMC loop (Section 2.4, Algorithm 2) with randomised Sobol'
-    point sets: while sum_l Var[Yhat_l] > eps^2 / 2, double the point set of
+  - mlqmc: the MLQMC loop (Section 2.4, Algorithm 2) with randomised point
+    sets, scrambled Sobol' with digital shifts or an embedded lattice sequence
+    with random shifts: while sum_l Var[Yhat_l] > eps^2 / 2, double the point set of
     the level maximising Var[Yhat_l] / (N_l C_l); then the same weak-error test.
 
 Every per-sample computation (field, FMG solve, Q) runs in the library; the
@@ -135,15 +136,26 @@ def mlmc(solve, eps, M, config, levels_available, n_init=64, L_init=2, alpha=Non
 
 
 def mlqmc(solve, eps, M, config, levels_available, m_init=6, nshift=16, L_init=2, alpha=None, gamma=2.0,
-          seed=inputs.SEED, max_rounds=200, m_max=20):
-    """Adaptive MLQMC with randomised Sobol' points: level l holds nshift x 2^m_l
-    samples (shift-major); Var[Yhat_l] is the variance of the mean over shifts."""
+          seed=inputs.SEED, max_rounds=200, m_max=None, rule="sobol"):
+    """Adaptive MLQMC: level l holds nshift x 2^m_l samples (shift-major) of
+    the randomised point set `rule` ("sobol" or "lattice"); Var[Yhat_l] is the
+    variance of the mean over shifts. m_max defaults to 20 (Sobol') or 16
+    (the lattice sequence's generating vector)."""
+    if rule not in ("sobol", "lattice"):
+        raise ValueError("rule must be 'sobol' or 'lattice'")
+    if m_max is None:
+        m_max = 20 if rule == "sobol" else 16
+    if rule == "sobol":
+        points = lambda l, m_from, m_to: inputs.rqmc_normals_range(M, m_from, m_to, nshift, config, l, seed)
+    else:
+        points = lambda l, m_from, m_to: inputs.lattice_normals_range(M, m_from, m_to, nshift, config, l, seed,
+                                                                      m_max=m_max)
     L = min(L_init, levels_available - 1)
     m = [m_init] * (L + 1)
     Y = [None] * (L + 1)                  # per level: [nshift, 2^m_l]
 
     def extend(l, m_from, m_to):
-        xi = inputs.rqmc_normals_range(M, m_from, m_to, nshift, config, l, seed)  # [R, count, M]
+        xi = points(l, m_from, m_to)  # [R, count, M]
         cnt = xi.shape[1]
         out = np.zeros((nshift, cnt))
         for r0 in range(0, nshift, max(1, CHUNK // max(cnt, 1))):

@@ -30,10 +30,13 @@ def oracle_solver():
     return solve
 
 
-@pytest.mark.parametrize("kind", ["mlmc", "mlqmc"])
+@pytest.mark.parametrize("kind", ["mlmc", "mlqmc", "mlqmc_lattice"])
 def test_driver_on_library_equals_driver_on_oracle(kind):
-    run = (lambda s: drivers.mlmc(s, 1e-2, M=16, config=9, levels_available=3, n_init=32)) if kind == "mlmc" else \
-          (lambda s: drivers.mlqmc(s, 4e-3, M=16, config=9, levels_available=3, m_init=4, nshift=8))
+    if kind == "mlmc":
+        run = lambda s: drivers.mlmc(s, 1e-2, M=16, config=9, levels_available=3, n_init=32)
+    else:
+        rule = "lattice" if kind == "mlqmc_lattice" else "sobol"
+        run = lambda s: drivers.mlqmc(s, 4e-3, M=16, config=9, levels_available=3, m_init=4, nshift=8, rule=rule)
     with fmgmc.Context(**CFG) as ctx:
         rg = run(drivers.library_solver(ctx))
     ro = run(oracle_solver())
