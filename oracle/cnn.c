@@ -125,7 +125,7 @@ void oracle_cnn_forward(int n, int B, int cin, int F, int R, const double *theta
 }
 
 /* FV operator of oracle.c (pinned by its closed forms) */
-void oracle_faces(int n, const double *K, double *Tx, double *Ty);
+void oracle_faces(int n, const double *K, int cs, double *Tx, double *Ty);
 void oracle_apply(int n, const double *Tx, const double *Ty, const double *x, double *y);
 
 /* Loss and its gradient with respect to the parameters (grad, same layout as
@@ -161,7 +161,7 @@ double oracle_cnn_loss_grad_kind(int n, int B, int cin, int F, int R, const doub
             /* u = x1 - A y; dL/dy = -2 A^T u / (B n^2), and A is symmetric */
             const double *x0 = x + (size_t)s * cin * N, *x1 = x0 + N;
             for (size_t k = 0; k < N; ++k) K[k] = exp(x0[k]);
-            oracle_faces(n, K, Tx, Ty);
+            oracle_faces(n, K, 2, Tx, Ty);
             oracle_apply(n, Tx, Ty, y, u);
             for (size_t k = 0; k < N; ++k) {
                 u[k] = x1[k] - u[k];

@@ -10,10 +10,12 @@
  *
  * Everything is written for clarity, in double precision, one sample at a
  * time, following the definitions in the order the paper states them:
- *   - model problem: Section 2.1, Eq. (1); Case II of Table 1 (Section 3.1):
- *     Dirichlet pressure on the west/east sides, no flow on north/south, QoI =
- *     outflow through the east side. The pressures are scaled to 1 and 0
- *     (the problem is linear, so the paper's 100/0 case is 100 times this).
+ *   - model problem: Section 2.1, Eq. (1); Cases I and II of Table 1
+ *     (Section 3.1). Case II: Dirichlet pressure on the west/east sides, no
+ *     flow on north/south, QoI = outflow through the east side. Case I:
+ *     Dirichlet pressure on all four sides, QoI = the pressure at the centre.
+ *     Boundary values are passed in; the problem is linear, so the paper's
+ *     values are a multiple of any scaled set (1/0 here for Case II).
  *   - discretisation: Section 3.1 (1), cell-centred finite volumes on a
  *     uniform n x n grid of the unit square, harmonic-mean face
  *     transmissibilities, half-cell transmissibility 2K on Dirichlet faces.
@@ -205,8 +207,16 @@ void oracle_coarsen(int n, const double *Kf, double *Kc)
 }
 
 /* ------------------------------------------------------------------------ */
-/* 2. Finite-volume operator (Section 3.1 (1), Case II of Table 1)          */
+/* 2. Finite-volume operator (Section 3.1 (1), Cases I and II of Table 1)   */
 /* ------------------------------------------------------------------------ */
+/*
+ * Boundary conditions (Table 1). `cs` selects the case:
+ *   cs = 2 (Case II): Dirichlet on the west and east sides, no flow through
+ *          the south and north sides; QoI = outflow through the east side;
+ *   cs = 1 (Case I):  Dirichlet on all four sides; QoI = u(1/2, 1/2).
+ * g[4] = Dirichlet values on the west, east, south and north sides (the
+ * south/north entries are unused in Case II).
+ */
 static double harmonic(double k1, double k2) { return 2.0 * k1 * k2 / (k1 + k2); }
 
 /*
@@ -215,10 +225,11 @@ static double harmonic(double k1, double k2) { return 2.0 * k1 * k2 / (k1 + k2);
  *   Tx[j][i], i = 0..n : face between cells i-1 and i of row j;
  *                        face 0 (west) and face n (east) are Dirichlet, 2K.
  *   Ty[j][i], j = 0..n : face between rows j-1 and j of column i;
- *                        faces 0 (south) and n (north) are no-flow, 0.
+ *                        faces 0 (south) and n (north) are no-flow, 0, in
+ *                        Case II and Dirichlet, 2K, in Case I.
  * Layout: Tx has (n+1) entries per row, Ty has n entries per face row.
  */
-void oracle_faces(int n, const double *K, double *Tx, double *Ty)
+void oracle_faces(int n, const double *K, int cs, double *Tx, double *Ty)
 {
     for (int j = 0; j < n; ++j) {
         const double *Kr = K + (size_t)j * n;
@@ -229,8 +240,8 @@ void oracle_faces(int n, const double *K, double *Tx, double *Ty)
         T[n] = 2.0 * Kr[n - 1];
     }
     for (int i = 0; i < n; ++i) {
-        Ty[i] = 0.0;
-        Ty[(size_t)n * n + i] = 0.0;
+        Ty[i] = (cs == 1) ? 2.0 * K[i] : 0.0;
+        Ty[(size_t)n * n + i] = (cs == 1) ? 2.0 * K[(size_t)(n - 1) * n + i] : 0.0;
     }
     for (int j = 1; j < n; ++j)
         for (int i = 0; i < n; ++i)
@@ -266,14 +277,16 @@ void oracle_apply(int n, const double *Tx, const double *Ty, const double *x, do
         }
 }
 
-/* Right-hand side: Dirichlet data enters through the west/east boundary faces. */
-void oracle_rhs(int n, const double *Tx, double pW, double pE, double *b)
+/* Right-hand side: Dirichlet data enters through the boundary faces that carry it. */
+void oracle_rhs(int n, const double *Tx, const double *Ty, const double *g, int cs, double *b)
 {
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) {
             double v = 0.0;
-            if (i == 0) v += Tx[(size_t)j * (n + 1)] * pW;
-            if (i == n - 1) v += Tx[(size_t)j * (n + 1) + n] * pE;
+            if (i == 0) v += Tx[(size_t)j * (n + 1)] * g[0];
+            if (i == n - 1) v += Tx[(size_t)j * (n + 1) + n] * g[1];
+            if (cs == 1 && j == 0) v += Ty[i] * g[2];
+            if (cs == 1 && j == n - 1) v += Ty[(size_t)n * n + i] * g[3];
             b[(size_t)j * n + i] = v;
         }
 }
@@ -289,12 +302,23 @@ void oracle_residual(int n, const double *Tx, const double *Ty, const double *b,
         }
 }
 
-/* Outflow through the east side (Case II QoI): sum_j T_east (p_{n-1,j} - pE). */
-double oracle_qoi(int n, const double *Tx, const double *x, double pE)
+/*
+ * QoI of Table 1.
+ * Case II: outflow through the east side, sum_j T_east (p_{n-1,j} - pE).
+ * Case I: u(1/2, 1/2). For even n the point is the corner shared by the four
+ * centre cells, and the bilinear interpolant of the cell values there is
+ * their mean.
+ */
+double oracle_qoi(int n, const double *Tx, const double *x, const double *g, int cs)
 {
+    if (cs == 1) {
+        int c = n / 2;
+        return 0.25 * (x[(size_t)(c - 1) * n + c - 1] + x[(size_t)(c - 1) * n + c]
+                       + x[(size_t)c * n + c - 1] + x[(size_t)c * n + c]);
+    }
     double q = 0.0;
     for (int j = 0; j < n; ++j)
-        q += Tx[(size_t)j * (n + 1) + n] * (x[(size_t)j * n + n - 1] - pE);
+        q += Tx[(size_t)j * (n + 1) + n] * (x[(size_t)j * n + n - 1] - g[1]);
     return q;
 }
 
@@ -336,45 +360,56 @@ void oracle_restrict(int n, const double *r, double *rc)
 
 /*
  * Value of a coarse-grid function outside the grid, for bilinear
- * interpolation: north/south (no flow) mirror the adjacent cell; west/east
- * (Dirichlet) use 2*g - value, where g is the boundary value (0 for a
- * correction, pW/pE for a solution).
+ * interpolation. A Dirichlet side with value g reflects oddly about it,
+ * 2 g - value; a no-flow side mirrors the adjacent cell. g is 0 for a
+ * correction and the boundary data for a solution. Outside in both
+ * directions (a corner), the south/north rule is applied first and the
+ * west/east rule to its result.
  */
-static double ghosted(int nc, const double *v, int I, int J, double gW, double gE)
+static double ghost_row(int nc, const double *v, int I, int J, const double *g, int cs)
 {
-    if (J < 0) J = 0;
-    if (J >= nc) J = nc - 1;
-    if (I < 0) return 2.0 * gW - v[(size_t)J * nc];
-    if (I >= nc) return 2.0 * gE - v[(size_t)J * nc + nc - 1];
-    return v[(size_t)J * nc + I];
+    if (J >= 0 && J < nc)
+        return v[(size_t)J * nc + I];
+    int Jc = J < 0 ? 0 : nc - 1;
+    if (cs == 1)
+        return 2.0 * (J < 0 ? g[2] : g[3]) - v[(size_t)Jc * nc + I];
+    return v[(size_t)Jc * nc + I];
+}
+
+static double ghosted(int nc, const double *v, int I, int J, const double *g, int cs)
+{
+    if (I < 0) return 2.0 * g[0] - ghost_row(nc, v, 0, J, g, cs);
+    if (I >= nc) return 2.0 * g[1] - ghost_row(nc, v, nc - 1, J, g, cs);
+    return ghost_row(nc, v, I, J, g, cs);
 }
 
 /* Bilinear cell-centred interpolation at fine cell (i,j): weights 9,3,3,1 / 16. */
-static double bilinear(int nc, const double *v, int i, int j, double gW, double gE)
+static double bilinear(int nc, const double *v, int i, int j, const double *g, int cs)
 {
     int I = i / 2, J = j / 2;
     int di = (i % 2) ? 1 : -1, dj = (j % 2) ? 1 : -1;
-    return (9.0 * ghosted(nc, v, I, J, gW, gE) + 3.0 * ghosted(nc, v, I + di, J, gW, gE)
-            + 3.0 * ghosted(nc, v, I, J + dj, gW, gE) + ghosted(nc, v, I + di, J + dj, gW, gE))
+    return (9.0 * ghosted(nc, v, I, J, g, cs) + 3.0 * ghosted(nc, v, I + di, J, g, cs)
+            + 3.0 * ghosted(nc, v, I, J + dj, g, cs) + ghosted(nc, v, I + di, J + dj, g, cs))
            / 16.0;
 }
 
 /* x (fine, n = 2 nc) += P ec, homogeneous boundary data. */
-void oracle_prolong_add(int nc, const double *ec, double *x)
+void oracle_prolong_add(int nc, const double *ec, int cs, double *x)
 {
+    static const double zero[4] = {0.0, 0.0, 0.0, 0.0};
     int n = 2 * nc;
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i)
-            x[(size_t)j * n + i] += bilinear(nc, ec, i, j, 0.0, 0.0);
+            x[(size_t)j * n + i] += bilinear(nc, ec, i, j, zero, cs);
 }
 
-/* FMG interpolation of a solution: x (fine) = P xc with Dirichlet data pW, pE. */
-void oracle_fmg_interp(int nc, const double *xc, double pW, double pE, double *x)
+/* FMG interpolation of a solution: x (fine) = P xc with the Dirichlet data g. */
+void oracle_fmg_interp(int nc, const double *xc, const double *g, int cs, double *x)
 {
     int n = 2 * nc;
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i)
-            x[(size_t)j * n + i] = bilinear(nc, xc, i, j, pW, pE);
+            x[(size_t)j * n + i] = bilinear(nc, xc, i, j, g, cs);
 }
 
 /* Dense Cholesky A = L L^T of the N = n*n coarsest operator (lower triangle in L). */
@@ -490,6 +525,7 @@ typedef struct {
     const double *chol; /* Cholesky factor of ops[0] */
     int nu1, nu2;
     int wmax;           /* coarse grids with n <= wmax are cycled twice (W-cycle) */
+    int cs;             /* boundary case (section 2 above) */
 } ovc;
 
 /*
@@ -519,7 +555,7 @@ static void vcycle(const ovc *V, int k, double *x, const double *b)
     vcycle(V, k - 1, C->x, C->b);
     if (C->n <= V->wmax && k - 1 > 0)
         vcycle(V, k - 1, C->x, C->b);
-    oracle_prolong_add(C->n, C->x, x);
+    oracle_prolong_add(C->n, C->x, V->cs, x);
     for (int s = 0; s < V->nu2; ++s) {
         oracle_rbgs_half(n, A->Tx, A->Ty, b, x, 0);
         oracle_rbgs_half(n, A->Tx, A->Ty, b, x, 1);
@@ -551,7 +587,7 @@ static double relres(const oop *A, double *r, const double *x, const double *b)
  * non-finite field) is reported through flags bit1.
  */
 int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fine,
-                      double pW, double pE, double tol, int max_cycles, int nu1, int nu2,
+                      const double *g, int cs, double tol, int max_cycles, int nu1, int nu2,
                       int wmax, double *qf, double *qc, int *cycles, int *flags, double *hist)
 {
     *qf = 0.0;
@@ -584,7 +620,7 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
         else
             oracle_coarsen(2 * n, K[k + 1], K[k]);
         op_alloc(&stage[k], n);
-        oracle_faces(n, K[k], stage[k].Tx, stage[k].Ty);
+        oracle_faces(n, K[k], cs, stage[k].Tx, stage[k].Ty);
         S[k].n = n;
         S[k].x = (double *)calloc((size_t)n * n, sizeof(double));
         S[k].b = (double *)calloc((size_t)n * n, sizeof(double));
@@ -620,11 +656,11 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
         oop *ops = (oop *)calloc(nlev, sizeof(oop));
         for (int k = 0; k <= top; ++k) {
             const oop *A = &stage[k];
-            oracle_rhs(A->n, A->Tx, pW, pE, bs);
+            oracle_rhs(A->n, A->Tx, A->Ty, g, cs, bs);
             if (k == 0)
                 memset(p, 0, sizeof(double) * (size_t)A->n * A->n);
             else
-                oracle_fmg_interp(stage[k - 1].n, pprev, pW, pE, p);
+                oracle_fmg_interp(stage[k - 1].n, pprev, g, cs, p);
 
             int is_fine = (k == top);
             int is_coarse = (level >= 1 && k == top - 1);
@@ -639,6 +675,7 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
             V.nu1 = nu1;
             V.nu2 = nu2;
             V.wmax = wmax;
+            V.cs = cs;
 
             if (is_fine || is_coarse) {
                 int slot = is_fine ? 1 : 0;
@@ -663,7 +700,7 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
                     *flags |= 2;
                 else if (rel > tol && k > 0)
                     *flags |= 1;
-                double qv = oracle_qoi(A->n, A->Tx, p, pE);
+                double qv = oracle_qoi(A->n, A->Tx, p, g, cs);
                 if (is_fine)
                     *qf = qv;
                 else
@@ -697,7 +734,7 @@ int oracle_fmg_sample(int n_fine, int n_coarsest, int level, const double *K_fin
  */
 int oracle_solve_level(double sigma2, double corr_len, int M, const int *a, const int *b,
                        const double *lam, int n_fine, int n_coarsest, int level,
-                       int64_t ns, const double *xi, double pW, double pE, double tol,
+                       int64_t ns, const double *xi, const double *g, int cs, double tol,
                        int max_cycles, int nu1, int nu2, int wmax, double *qf, double *qc,
                        int *cycles, int *flags, int nthreads)
 {
@@ -713,7 +750,7 @@ int oracle_solve_level(double sigma2, double corr_len, int M, const int *a, cons
     for (int64_t s = 0; s < ns; ++s) {
         double *K = (double *)malloc(sizeof(double) * (size_t)n_fine * n_fine);
         oracle_field(n_fine, corr_len, M, a, b, lam, xi + (size_t)s * M, K);
-        int r = oracle_fmg_sample(n_fine, n_coarsest, level, K, pW, pE, tol, max_cycles,
+        int r = oracle_fmg_sample(n_fine, n_coarsest, level, K, g, cs, tol, max_cycles,
                                   nu1, nu2, wmax, &qf[s], &qc[s], &cycles[2 * s], &flags[s], NULL);
         if (r != 0)
             err |= 1;

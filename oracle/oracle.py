@@ -36,21 +36,21 @@ def lib():
             "oracle_kl_table": (_i, [_d, _d, _i, _pi, _pi, _pd]),
             "oracle_field": (None, [_i, _d, _i, _pi, _pi, _pd, _pd, _pd]),
             "oracle_coarsen": (None, [_i, _pd, _pd]),
-            "oracle_faces": (None, [_i, _pd, _pd, _pd]),
+            "oracle_faces": (None, [_i, _pd, _i, _pd, _pd]),
             "oracle_apply": (None, [_i, _pd, _pd, _pd, _pd]),
-            "oracle_rhs": (None, [_i, _pd, _d, _d, _pd]),
+            "oracle_rhs": (None, [_i, _pd, _pd, _pd, _i, _pd]),
             "oracle_residual": (None, [_i, _pd, _pd, _pd, _pd, _pd]),
-            "oracle_qoi": (_d, [_i, _pd, _pd, _d]),
+            "oracle_qoi": (_d, [_i, _pd, _pd, _pd, _i]),
             "oracle_rbgs_half": (None, [_i, _pd, _pd, _pd, _pd, _i]),
             "oracle_restrict": (None, [_i, _pd, _pd]),
-            "oracle_prolong_add": (None, [_i, _pd, _pd]),
-            "oracle_fmg_interp": (None, [_i, _pd, _d, _d, _pd]),
+            "oracle_prolong_add": (None, [_i, _pd, _i, _pd]),
+            "oracle_fmg_interp": (None, [_i, _pd, _pd, _i, _pd]),
             "oracle_chol_factor": (_i, [_i, _pd, _pd, _pd]),
             "oracle_chol_solve": (None, [_i, _pd, _pd, _pd]),
             "oracle_coarsen_faces": (None, [_i, _pd, _pd, _pd, _pd]),
-            "oracle_fmg_sample": (_i, [_i, _i, _i, _pd, _d, _d, _d, _i, _i, _i, _i,
+            "oracle_fmg_sample": (_i, [_i, _i, _i, _pd, _pd, _i, _d, _i, _i, _i, _i,
                                        C.POINTER(_d), C.POINTER(_d), _pi, C.POINTER(_i), C.c_void_p]),
-            "oracle_solve_level": (_i, [_d, _d, _i, _pi, _pi, _pd, _i, _i, _i, _i64, _pd, _d, _d,
+            "oracle_solve_level": (_i, [_d, _d, _i, _pi, _pi, _pd, _i, _i, _i, _i64, _pd, _pd, _i,
                                         _d, _i, _i, _i, _i, _pd, _pd, _pi, _pi, _i]),
             "oracle_max_threads": (_i, []),
             "oracle_sum": (_d, [_i64, _pd]),
@@ -114,47 +114,58 @@ def coarsen(Kf):
 
 
 # --- finite volumes ------------------------------------------------------
-def faces(K):
+# Boundary case of Table 1: 2 = Case II (Dirichlet west/east, no flow south/north,
+# east outflow), 1 = Case I (Dirichlet on all sides, centre pressure). Boundary
+# values (west, east, south, north); the Case I defaults are the paper's
+# 100/0/10/50 scaled by 1/100, as Case II's 1/0 is its 100/0.
+CASE1_G = (1.0, 0.0, 0.1, 0.5)
+
+
+def _g(pW, pE, pS=0.0, pN=0.0):
+    return np.array([pW, pE, pS, pN], dtype=np.float64)
+
+
+def faces(K, case=2):
     n = K.shape[0]
     Tx = np.zeros((n, n + 1))
     Ty = np.zeros((n + 1, n))
-    lib().oracle_faces(n, _f64(K), Tx, Ty)
+    lib().oracle_faces(n, _f64(K), int(case), Tx, Ty)
     return Tx, Ty
 
 
-def apply(K, x, fc=None):
+def apply(K, x, fc=None, case=2):
     n = K.shape[0]
-    Tx, Ty = fc if fc is not None else faces(K)
+    Tx, Ty = fc if fc is not None else faces(K, case)
     y = np.zeros((n, n))
     lib().oracle_apply(n, Tx, Ty, _f64(x), y)
     return y
 
 
-def rhs(K, pW=1.0, pE=0.0):
+def rhs(K, pW=1.0, pE=0.0, case=2, pS=0.0, pN=0.0):
     n = K.shape[0]
-    Tx, _ = faces(K)
+    Tx, Ty = faces(K, case)
     b = np.zeros((n, n))
-    lib().oracle_rhs(n, Tx, pW, pE, b)
+    lib().oracle_rhs(n, Tx, Ty, _g(pW, pE, pS, pN), int(case), b)
     return b
 
 
-def residual(K, b, x):
+def residual(K, b, x, case=2):
     n = K.shape[0]
-    Tx, Ty = faces(K)
+    Tx, Ty = faces(K, case)
     r = np.zeros((n, n))
     lib().oracle_residual(n, Tx, Ty, _f64(b), _f64(x), r)
     return r
 
 
-def qoi(K, x, pE=0.0):
+def qoi(K, x, pE=0.0, case=2):
     n = K.shape[0]
-    Tx, _ = faces(K)
-    return lib().oracle_qoi(n, Tx, _f64(x), pE)
+    Tx, _ = faces(K, case)
+    return lib().oracle_qoi(n, Tx, _f64(x), _g(0.0, pE), int(case))
 
 
-def rbgs_half(K, b, x, colour):
+def rbgs_half(K, b, x, colour, case=2):
     n = K.shape[0]
-    Tx, Ty = faces(K)
+    Tx, Ty = faces(K, case)
     x = _f64(x).copy()
     lib().oracle_rbgs_half(n, Tx, Ty, _f64(b), x, colour)
     return x
@@ -167,22 +178,22 @@ def restrict(r):
     return rc
 
 
-def prolong_add(ec, x):
+def prolong_add(ec, x, case=2):
     x = _f64(x).copy()
-    lib().oracle_prolong_add(ec.shape[0], _f64(ec), x)
+    lib().oracle_prolong_add(ec.shape[0], _f64(ec), int(case), x)
     return x
 
 
-def fmg_interp(xc, pW=1.0, pE=0.0):
+def fmg_interp(xc, pW=1.0, pE=0.0, case=2, pS=0.0, pN=0.0):
     nc = xc.shape[0]
     x = np.zeros((2 * nc, 2 * nc))
-    lib().oracle_fmg_interp(nc, _f64(xc), pW, pE, x)
+    lib().oracle_fmg_interp(nc, _f64(xc), _g(pW, pE, pS, pN), int(case), x)
     return x
 
 
-def chol_solve(K, b):
+def chol_solve(K, b, case=2):
     n = K.shape[0]
-    Tx, Ty = faces(K)
+    Tx, Ty = faces(K, case)
     L = np.zeros((n * n, n * n))
     if lib().oracle_chol_factor(n, Tx, Ty, L) != 0:
         raise ValueError("not positive definite")
@@ -195,16 +206,26 @@ def chol_solve(K, b):
 W_MAX = 64  # coarse grids with n <= 64 get W-cycle (two) coarse-grid corrections
 
 
-def fmg_sample(K, level, tol=1e-10, max_cycles=50, nu1=2, nu2=2, pW=1.0, pE=0.0,
-               n_coarsest=4, history=False, wmax=W_MAX):
+def boundary(case, pW=None, pE=None, pS=None, pN=None):
+    """(g[4], case) with the defaults of the case filled in."""
+    d = CASE1_G if case == 1 else (1.0, 0.0, 0.0, 0.0)
+    v = [d[k] if x is None else float(x) for k, x in enumerate((pW, pE, pS, pN))]
+    if case not in (1, 2):
+        raise ValueError("case must be 1 or 2")
+    return _g(*v), int(case)
+
+
+def fmg_sample(K, level, tol=1e-10, max_cycles=50, nu1=2, nu2=2, pW=None, pE=None,
+               n_coarsest=4, history=False, wmax=W_MAX, case=2, pS=None, pN=None):
     """One FMG pass; returns dict(qf, qc, cycles, flags[, hist])."""
+    g, cs = boundary(case, pW, pE, pS, pN)
     n = K.shape[0]
     qf = C.c_double()
     qc = C.c_double()
     cyc = np.zeros(2, np.int32)
     fl = C.c_int()
     hist = np.zeros(2 * max_cycles) if history else None
-    rc = lib().oracle_fmg_sample(n, n_coarsest, level, _f64(K), pW, pE, tol, max_cycles,
+    rc = lib().oracle_fmg_sample(n, n_coarsest, level, _f64(K), g, cs, tol, max_cycles,
                                  nu1, nu2, wmax, C.byref(qf), C.byref(qc), cyc, C.byref(fl),
                                  hist.ctypes.data if history else None)
     out = dict(qf=qf.value, qc=qc.value, cycles=cyc, flags=fl.value, rc=rc)
@@ -214,8 +235,10 @@ def fmg_sample(K, level, tol=1e-10, max_cycles=50, nu1=2, nu2=2, pW=1.0, pE=0.0,
 
 
 def solve_level(sigma2, corr_len, table, n_fine, level, xi, tol=1e-10, max_cycles=50,
-                nu1=2, nu2=2, pW=1.0, pE=0.0, n_coarsest=4, nthreads=0, wmax=W_MAX):
+                nu1=2, nu2=2, pW=None, pE=None, n_coarsest=4, nthreads=0, wmax=W_MAX, case=2,
+                pS=None, pN=None):
     """Batched oracle: xi [ns, M] -> qf, qc [ns], cycles [ns, 2], flags [ns]."""
+    g, cs = boundary(case, pW, pE, pS, pN)
     a, b, lam = table
     xi = _f64(xi)
     ns = xi.shape[0]
@@ -224,7 +247,7 @@ def solve_level(sigma2, corr_len, table, n_fine, level, xi, tol=1e-10, max_cycle
     cyc = np.zeros((ns, 2), np.int32)
     fl = np.zeros(ns, np.int32)
     rc = lib().oracle_solve_level(sigma2, corr_len, len(a), a, b, lam, n_fine, n_coarsest,
-                                  level, ns, xi, pW, pE, tol, max_cycles, nu1, nu2, wmax, qf, qc,
+                                  level, ns, xi, g, cs, tol, max_cycles, nu1, nu2, wmax, qf, qc,
                                   cyc, fl, nthreads)
     if rc != 0:
         raise RuntimeError("oracle_solve_level failed")
