@@ -504,6 +504,55 @@ def report_saving(torch, fmgmc, inputs, args):
                                    "rel-res 1e-10, one device batch per level"}}
 
 
+def report_case1(torch, fmgmc, inputs, args):
+    """Case I of Table 1 (Dirichlet on all four sides, the paper's 100/0/10/50 scaled by
+    1/100; QoI = u(1/2, 1/2)) on the headline workload: 512^2 level of the 5-level
+    config, 4096 samples, rel-res 1e-10; Case II (the headline problem) run beside it on
+    the same box, and a sampled check against the oracle."""
+    cfg = dict(CFG)
+    S = args.samples
+    xi_host = inputs.mc_normals(S, cfg["n_modes"], config=2, level=LEVEL)
+    xi = _dev(torch, xi_host)
+    res = {}
+    for case in (1, 2):
+        for form in ("fp32_ir", "fp64"):
+            kw = dict(inner_first=args.inner_first, inner_cycles=args.inner) if form == "fp32_ir" else {}
+            with fmgmc.Context(**cfg, solver=form, max_batch=S, max_cycles=60, w_max_n=args.wmax, case=case,
+                               rel_tol=args.tol, **kw) as ctx:
+                qf, qc, cyc, fl = _bufs(torch, S)
+                ctx.solve_level(LEVEL, xi, qf, qc, cyc, fl)
+                t0 = _t(torch)
+                for _ in range(args.steps):
+                    ctx.solve_level(LEVEL, xi, qf, qc, cyc, fl)
+                dt = (_t(torch) - t0) / args.steps
+                est = fmgmc.estimate([qf], [qc])["levels"][0]
+            key = f"case{case}_{form}"
+            res[key] = dict(samples_per_s=round(S / dt, 1), ms_per_step=round(1e3 * dt, 2),
+                            cycles_mean=[round(float(x), 3) for x in cyc.double().mean(0).cpu().numpy()],
+                            flagged=int(((fl & 3) != 0).sum().item()), mean_qf=float(qf.double().mean().item()),
+                            mean_y=est["mean_y"], var_y=est["var_y"])
+            if case == 1 and form == "fp64":
+                pick = [0, 1000, 4095]
+                of, oc, ocyc = _oracle_case1(cfg, xi_host[pick], args.tol, args.wmax)
+                res[key]["cycles_gpu_vs_oracle"] = [cyc.cpu().numpy()[pick].tolist(), ocyc.tolist()]
+                res[key]["qf_rel_err_vs_oracle"] = _rel(qf.cpu().numpy()[pick], of)
+                res[key]["qc_rel_err_vs_oracle"] = _rel(qc.cpu().numpy()[pick], oc)
+            log(f"case {case} {form}: {res[key]['samples_per_s']} samples/s")
+    return {"metric": "Case I FMG-MLMC level throughput", "value": res["case1_fp32_ir"]["samples_per_s"],
+            "unit": "samples/s", "forms": res,
+            "config": {"workload": f"Case I (Dirichlet 1/0/0.1/0.5 on W/E/S/N, QoI u(1/2,1/2)) on the 512^2 level "
+                                   f"of the 5-level config, sigma2=1, corr_len=0.2, 256 KL modes, {S} samples, "
+                                   f"rel-res {args.tol:g}; Case II beside it"}}
+
+
+def _oracle_case1(cfg, xi, tol, wmax):
+    from oracle import oracle as O
+    tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
+    qf, qc, cyc, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], tab, N, LEVEL, xi, tol=tol, case=1, wmax=wmax,
+                                   nthreads=O.max_threads())
+    return qf, qc, cyc
+
+
 def report_adaptive(torch, fmgmc, inputs, args):
     """The adaptive FMG-MLMC (Algorithms 1 and 3) and MLQMC (Algorithm 2) drivers on the
     library: 7-level hierarchy 8^2 .. 512^2 of the 5-level field (sigma2=1, corr_len=0.2,
@@ -534,7 +583,7 @@ def report_adaptive(torch, fmgmc, inputs, args):
                                    "2^m x 16 shifts doubled per level"}}
 
 
-REPORTS = {"cfg1": report_cfg1, "saving": report_saving, "adaptive": report_adaptive, "cfg2": report_cfg2, "cfg3": report_cfg3, "cfg4": report_cfg4,
+REPORTS = {"case1": report_case1, "cfg1": report_cfg1, "saving": report_saving, "adaptive": report_adaptive, "cfg2": report_cfg2, "cfg3": report_cfg3, "cfg4": report_cfg4,
            "cfg5": report_cfg5}
 
 

@@ -3,9 +3,11 @@
  * multilevel (quasi-)Monte Carlo method for single-phase Darcy flow with a
  * log-normal random permeability (Liu, Li, Sun, Yu, arXiv:1910.04727).
  *
- * Problem solved per sample (Section 2.1 Eq. (1); Case II of Table 1):
- *   -div(k grad p) = 0 on the unit square, p = p_west on x = 0, p = p_east on
- *   x = 1, no flow on y = 0 and y = 1; QoI = outflow through x = 1.
+ * Problem solved per sample (Section 2.1 Eq. (1); Table 1):
+ *   -div(k grad p) = 0 on the unit square. Case II: p = p_west on x = 0,
+ *   p = p_east on x = 1, no flow on y = 0 and y = 1; QoI = outflow through
+ *   x = 1. Case I: p = p_west / p_east / p_south / p_north on x = 0 / x = 1 /
+ *   y = 0 / y = 1; QoI = p(1/2, 1/2).
  *   Cell-centred finite volumes on an n x n grid with harmonic-mean face
  *   transmissibilities (Section 3.1 (1)).
  * Field (Section 3.1 (2)): k = exp(g), g a truncated Karhunen-Loeve expansion
@@ -74,14 +76,23 @@ typedef struct {
     int32_t cov_kind;  /* FMGMC_COV_SEPARABLE_EXP */
 } fmgmc_field;
 
-/* Level hierarchy (Section 3.1 (1)). */
+/* Boundary conditions and QoI (Table 1). MIXED, Case II: Dirichlet pressure on
+ * the west and east sides, no flow through the south and north sides, QoI =
+ * outflow through the east side. DIRICHLET, Case I: Dirichlet pressure on all
+ * four sides, QoI = u(1/2, 1/2), the mean of the four centre cells (the point
+ * is their shared corner). */
+enum { FMGMC_BC_MIXED = 0, FMGMC_BC_DIRICHLET = 1 };
+
+/* Level hierarchy and boundary data (Section 3.1 (1), Table 1). */
 typedef struct {
     int32_t n_levels;    /* MLMC levels 0 .. n_levels-1 */
     int32_t n0;          /* fine grid of level 0 (power of two); level l uses n0 << l */
     int32_t n_coarsest;  /* multigrid coarsest grid, 4; n0 >= n_coarsest */
-    int32_t reserved;    /* 0 */
+    int32_t boundary;    /* FMGMC_BC_MIXED (0) or FMGMC_BC_DIRICHLET */
     double p_west;       /* Dirichlet pressure at x = 0 */
     double p_east;       /* Dirichlet pressure at x = 1 */
+    double p_south;      /* Dirichlet pressure at y = 0 (FMGMC_BC_DIRICHLET only) */
+    double p_north;      /* Dirichlet pressure at y = 1 (FMGMC_BC_DIRICHLET only) */
 } fmgmc_hier;
 
 /* Solver options. */
@@ -320,6 +331,8 @@ int fmgmc_cnn_train(fmgmc_ctx *ctx, fmgmc_cnn *cnn, int32_t level, int64_t n_sam
  * Uses `cnn` (NULL: off) to warm-start every QoI stage with n >= min_n in the
  * FP32_IR solver. The context keeps the pointer; the caller keeps the
  * network alive and does not train it while the context solves.
+ * The network calls (make_data, train, set_warm_start) take Case II
+ * contexts only (FMGMC_EINVAL otherwise): its residual loss is that operator.
  */
 int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n);
 

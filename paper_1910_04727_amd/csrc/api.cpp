@@ -139,7 +139,9 @@ void free_work(Work &w) {
         dfree(w.x32[k]); dfree(w.b32[k]);
         for (int q = 0; q < 2; ++q) {
             dfree(w.pf64[q].f[k].fx); dfree(w.pf64[q].f[k].fy); dfree(w.pf64[q].f[k].fxe);
+            dfree(w.pf64[q].f[k].fyn);
             dfree(w.pf32[q].f[k].fx); dfree(w.pf32[q].f[k].fy); dfree(w.pf32[q].f[k].fxe);
+            dfree(w.pf32[q].f[k].fyn);
         }
     }
     dfree(w.chol); dfree(w.rr); dfree(w.q); dfree(w.bnorm); dfree(w.qf); dfree(w.qc); dfree(w.xi);
@@ -192,11 +194,17 @@ namespace {
 
 bool ir_mode(const fmgmc_ctx *c) { return c->opts.solver == FMGMC_SOLVER_FP32_IR; }
 
+Bnd bnd(const fmgmc_ctx *c) {
+    const fmgmc_hier &h = c->hier;
+    return Bnd{h.p_west, h.p_east, h.p_south, h.p_north, h.boundary == FMGMC_BC_DIRICHLET ? 1 : 0};
+}
+
 template <typename T>
 int alloc_faces(Faces<T> &f, int S, int n) {
     TRY(dalloc(&f.fx, size_t(S) * n * n));
     TRY(dalloc(&f.fy, size_t(S) * n * n));
     TRY(dalloc(&f.fxe, size_t(S) * n));
+    TRY(dalloc(&f.fyn, size_t(S) * n));
     return FMGMC_OK;
 }
 
@@ -309,7 +317,7 @@ int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool
            hipStream_t st) {
     const int nh1 = 2 * c->opts.nu1, nh2 = 2 * c->opts.nu2;
     const int N0 = W.nsz[0] * W.nsz[0];
-    const double pW = c->hier.p_west, pE = c->hier.p_east;
+    const Bnd g = bnd(c);
     const double *chol_pyr = W.chol + size_t(1 + q) * S * N0 * N0;
     const double *chol_stage = W.chol;
     auto gamma = [&](int j) { return (j > 0 && W.nsz[j] <= c->opts.w_max_n) ? 2 : 1; };
@@ -327,8 +335,7 @@ int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool
         a.rr = W.rr;
         a.q = W.q;
         a.active = W.active;
-        a.pW = pW;
-        a.pE = pE;
+        a.g = g;
         a.nu1 = c->opts.nu1;
         a.nu2 = c->opts.nu2;
         a.wmax = c->opts.w_max_n;
@@ -350,8 +357,7 @@ int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool
         a.rr = W.rr;
         a.q = W.q;
         a.active = W.active;
-        a.pW = pW;
-        a.pE = pE;
+        a.g = g;
         return launch_march(a, S, nh, ck, minit, rhsa, mout, st);
     };
     // cycle rooted at correction level j (rhs b[j], faces of pyramid q)
@@ -438,18 +444,19 @@ int run_block(Work &W, bool use_graph, std::tuple<int, int, int, int> key, hipSt
 // Build correction pyramids and coarsest inverses for a batch.
 template <typename T>
 int prepare(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int level, int t, hipStream_t st) {
-    (void)c;
+    const int all = bnd(c).all;
     const int N0 = W.nsz[0] * W.nsz[0];
     Faces<T> none{};
-    TRY(launch_chol<T>(W.nsz[0], B.K[0], none, true, W.chol, S, st));
+    TRY(launch_chol<T>(W.nsz[0], B.K[0], none, true, all, W.chol, S, st));
     for (int q = 0; q < 2; ++q) {
         const int top = (q == 1) ? t : t - 1;  // QoI stage that owns the pyramid
         if (q == 0 && level == 0) continue;
         if (top < 1) continue;
-        TRY(launch_faces_from_k<T>(W.nsz[top], B.K[top], B.pf[q].f[top - 1], S, st));
+        TRY(launch_faces_from_k<T>(W.nsz[top], B.K[top], all, B.pf[q].f[top - 1], S, st));
         for (int j = top - 1; j >= 1; --j)
             TRY(launch_faces_coarsen<T>(W.nsz[j], B.pf[q].f[j], B.pf[q].f[j - 1], S, st));
-        TRY(launch_chol<T>(W.nsz[0], nullptr, B.pf[q].f[0], false, W.chol + size_t(1 + q) * S * N0 * N0, S, st));
+        TRY(launch_chol<T>(W.nsz[0], nullptr, B.pf[q].f[0], false, all, W.chol + size_t(1 + q) * S * N0 * N0, S,
+                           st));
     }
     return FMGMC_OK;
 }
@@ -507,7 +514,7 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
             }
             double *qout = fine ? qtop : qc;
             const int slot = fine ? slot_top : 0;
-            TRY(launch_bnorm<double>(W.nsz[k], B.K[k], c->hier.p_west, c->hier.p_east, W.bnorm, S, st));
+            TRY(launch_bnorm<double>(W.nsz[k], B.K[k], bnd(c), W.bnorm, S, st));
             int na;
             if (k == 0) {  // direct solve: exact, no cycles
                 TRY(vcycle<double>(c, W, B, S, 0, q, INIT_ZERO, false, OUT_RR | OUT_Q, st));
@@ -574,7 +581,7 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
     Bufs<float> B = bufs32(W);
     TRY(prepare<float>(c, W, B, S, level, t, st));
     const double tol = c->opts.rel_tol;
-    const double pW = c->hier.p_west, pE = c->hier.p_east;
+    const Bnd g = bnd(c);
     // one FMG pass up to stage ktop; with_coarse: stage ktop - 1 is a QoI stage too
     auto pass = [&](int ktop, bool with_coarse, double *qtop, int slot_top) -> int {
         for (int k = 0; k <= ktop; ++k) {
@@ -591,11 +598,11 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             const int n = W.nsz[k];
             // FMG start in FP64: from the FP64 solution when the stage below was a QoI stage
             auto interp = [&]() -> int {
-                if (fine && with_coarse) return launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, pW, pE, S, st);
-                return launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, pW, pE, S, st);
+                if (fine && with_coarse) return launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, g, S, st);
+                return launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, g, S, st);
             };
             TRY(interp());
-            TRY(launch_bnorm<double>(n, W.K64[k], pW, pE, W.bnorm, S, st));
+            TRY(launch_bnorm<double>(n, W.K64[k], g, W.bnorm, S, st));
             IRArgs ia{};
             ia.n = n;
             ia.p = W.p64[k];
@@ -605,8 +612,7 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             ia.rr = W.rr;
             ia.q = W.q;
             ia.active = W.active;
-            ia.pW = pW;
-            ia.pE = pE;
+            ia.g = g;
             {
                 // first residual of the stage: reads p and K, writes r (20 B per cell)
                 const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
@@ -652,6 +658,10 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
         f->n_modes > 4096)
         return FMGMC_EINVAL;
     if (h->n_levels < 1 || !pow2(h->n0) || h->n_coarsest != 4 || h->n0 < h->n_coarsest) return FMGMC_EINVAL;
+    if (h->boundary != FMGMC_BC_MIXED && h->boundary != FMGMC_BC_DIRICHLET) return FMGMC_EINVAL;
+    if (!std::isfinite(h->p_west) || !std::isfinite(h->p_east) || !std::isfinite(h->p_south) ||
+        !std::isfinite(h->p_north))
+        return FMGMC_EINVAL;
     const int nf = h->n0 << (h->n_levels - 1);
     if (nf > 1024) return FMGMC_EINVAL;
     if (o->solver != FMGMC_SOLVER_FP64 && o->solver != FMGMC_SOLVER_FP32_IR) return FMGMC_EINVAL;
@@ -1101,8 +1111,9 @@ int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params) {
 }
 
 int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n) {
-    if (!ctx || min_n < 16 || (cnn && !ir_mode(ctx)) || (cnn && cnn->device != ctx->device)) {
-        set_error("fmgmc_set_warm_start: bad arguments (FP32_IR solver, min_n >= 16, same device)");
+    if (!ctx || min_n < 16 || (cnn && !ir_mode(ctx)) || (cnn && cnn->device != ctx->device) ||
+        (cnn && ctx->hier.boundary != FMGMC_BC_MIXED)) {
+        set_error("fmgmc_set_warm_start: bad arguments (FP32_IR solver, Case II boundaries, min_n >= 16, same device)");
         return FMGMC_EINVAL;
     }
     DevGuard g(ctx->device);
@@ -1118,8 +1129,8 @@ int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n) {
 int fmgmc_cnn_make_data(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const double *xi, float *x_coarse,
                         float *t_coarse, float *x_fine, float *t_fine, void *stream) {
     if (!ctx || level < 0 || level >= ctx->hier.n_levels || n_samples < 1 || !xi || !x_fine || !t_fine ||
-        !ir_mode(ctx) || (!x_coarse) != (!t_coarse)) {
-        set_error("fmgmc_cnn_make_data: bad arguments (FP32_IR solver)");
+        !ir_mode(ctx) || (!x_coarse) != (!t_coarse) || ctx->hier.boundary != FMGMC_BC_MIXED) {
+        set_error("fmgmc_cnn_make_data: bad arguments (FP32_IR solver, Case II boundaries)");
         return FMGMC_EINVAL;
     }
     const int n = ctx->hier.n0 << level;
@@ -1155,8 +1166,8 @@ int fmgmc_cnn_make_data(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const 
 int fmgmc_cnn_train(fmgmc_ctx *ctx, fmgmc_cnn *cnn, int32_t level, int64_t n_samples, const double *xi,
                     int32_t batch, double lr, double *loss_hist) {
     if (!ctx || !cnn || level < 0 || level >= ctx->hier.n_levels || n_samples < 1 || !xi || batch < 1 ||
-        !(lr > 0) || cnn->device != ctx->device) {
-        set_error("fmgmc_cnn_train: bad arguments");
+        !(lr > 0) || cnn->device != ctx->device || ctx->hier.boundary != FMGMC_BC_MIXED) {
+        set_error("fmgmc_cnn_train: bad arguments (the network's residual loss is Case II's operator)");
         return FMGMC_EINVAL;
     }
     DevGuard g(ctx->device);

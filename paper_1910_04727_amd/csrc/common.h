@@ -33,12 +33,23 @@ int build_mode_table(double sigma2, double corr_len, int M, ModeTable &t);
 void tabulate_phi(const ModeTable &t, int n, std::vector<double> &tab);
 
 // ---------------------------------------------------------------- kernels
+// Boundary conditions (Table 1): Dirichlet values on the west, east, south and
+// north sides. all = 0: Case II (no flow through the south and north sides, QoI
+// = outflow through the east side); all = 1: Case I (Dirichlet on every side,
+// QoI = pressure at the centre, the mean of the four centre cells).
+struct Bnd {
+    double w, e, s, n;
+    int all;
+};
+
 // Per-level views of a batch (S samples, grid n x n, sample stride n*n).
 template <typename T>
 struct Faces {
     T *fx;    // [S][n][n] west face of each cell (face i of row j)
-    T *fy;    // [S][n][n] south face of each cell (face j of column i); row 0 is 0
+    T *fy;    // [S][n][n] south face of each cell (face j of column i); row 0 is the
+              //           south boundary face (0 in Case II)
     T *fxe;   // [S][n]    east boundary face of each row
+    T *fyn;   // [S][n]    north boundary face of each column (0 in Case II)
 };
 
 // march kernels: one workgroup per sample marching over the rows
@@ -55,9 +66,9 @@ struct MarchArgs {
     const T *xc;          // [S][n/2][n/2] coarse correction (PROLONG) or solution (INTERP)
     T *bc;                // [S][n/2][n/2] restricted residual (OUT_RESTRICT)
     double *rr;           // [S] sum of squared residuals (OUT_RR)
-    double *q;            // [S] east outflow (OUT_Q)
+    double *q;            // [S] QoI (OUT_Q)
     const int32_t *active;// [S] nonzero = sample still iterating
-    double pW, pE;
+    Bnd g;
 };
 
 // Launches one fused smoothing pass; nhalf = number of half-sweeps (2 nu),
@@ -69,7 +80,7 @@ int launch_march(const MarchArgs<T> &a, int S, int nhalf, bool coef_from_k, int 
 
 // face pyramid: from the stage operator on n (K) or from faces on n, to faces on n/2
 template <typename T>
-int launch_faces_from_k(int n, const T *K, Faces<T> out, int S, hipStream_t st);
+int launch_faces_from_k(int n, const T *K, int all, Faces<T> out, int S, hipStream_t st);
 template <typename T>
 int launch_faces_coarsen(int n, Faces<T> in, Faces<T> out, int S, hipStream_t st);
 
@@ -88,7 +99,7 @@ struct SmallArgs {
     double *rr;
     double *q;
     const int32_t *active;
-    double pW, pE;
+    Bnd g;
     int nu1, nu2;
     int wmax;             // coarse grids with n <= wmax (not the coarsest) are cycled twice
 };
@@ -98,7 +109,7 @@ int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out
 // Inverse of the coarsest operator (n0 x n0 grid, n0^2 <= 16) from K or faces,
 // through its Cholesky factor, in FP64.
 template <typename T>
-int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, double *L, int S, hipStream_t st);
+int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, int all, double *L, int S, hipStream_t st);
 
 // KL synthesis: K_top (and its injected pyramid) from xi.
 struct KLArgs {
@@ -128,18 +139,18 @@ struct IRArgs {
     float *r32;
     double *rr, *q;
     const int32_t *active;
-    double pW, pE;
+    Bnd g;
 };
 int launch_ir(const IRArgs &a, int S, hipStream_t st);
 
 // p64 (n) = FMG interpolation of xc (n/2), xc float or double
 template <typename TS>
-int launch_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE,
-                    int S, hipStream_t st);
+int launch_interp64(int n, const TS *xc, double *p, const int32_t *active, const Bnd &g, int S,
+                    hipStream_t st);
 
-// ||b||_2 of the stage right-hand side (Dirichlet data through the side faces)
+// ||b||_2 of the stage right-hand side (Dirichlet data through the boundary faces)
 template <typename T>
-int launch_bnorm(int n, const T *K, double pW, double pE, double *bn, int S, hipStream_t st);
+int launch_bnorm(int n, const T *K, const Bnd &g, double *bn, int S, hipStream_t st);
 
 // convergence bookkeeping for one QoI stage after a cycle
 struct CheckArgs {

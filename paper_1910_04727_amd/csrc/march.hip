@@ -12,10 +12,14 @@
 // residual follows at row F - NH - 1 and is summed over 2x2 blocks into the
 // next coarser grid and/or squared into the sample's residual norm. Every
 // cell is read and written once per pass.
-// Rows in flight live in an LDS ring padded with a zero column on each side
-// (so boundary neighbours contribute nothing without a branch); per-row
+// Rows in flight live in an LDS ring padded with a zero column on each side,
+// and the ring rows below row 0 and above row n-1 read as zero when those rows
+// are swept, so boundary neighbours contribute nothing without a branch (a
+// boundary face enters only the diagonal and the right-hand side); per-row
 // coefficients live in a register ring. One barrier per row step: every
 // cross-lane read in step F is of data written before step F's barrier.
+// Boundary conditions: Case II (Dirichlet west/east, no flow south/north) or
+// Case I (Dirichlet on all sides) of Table 1, a uniform runtime switch.
 #include <type_traits>
 
 #include "common.h"
@@ -104,8 +108,10 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
 
     const size_t base = size_t(s) * n * n;
     const size_t cbase = size_t(s) * nc * nc;
-    const T gW = T(A.pW), gE = T(A.pE);
+    const T gW = T(A.g.w), gE = T(A.g.e), gS = T(A.g.s), gN = T(A.g.n);
+    const bool dns = A.g.all != 0;  // Dirichlet south / north sides (Case I)
     const T cgW = (INIT == INIT_INTERP) ? gW : T(0), cgE = (INIT == INIT_INTERP) ? gE : T(0);
+    const T cgS = (INIT == INIT_INTERP) ? gS : T(0), cgN = (INIT == INIT_INTERP) ? gN : T(0);
     const bool first = (l == 0), last = (l == nl - 1);
 
     // prefetch queue, slot = row % U
@@ -162,15 +168,33 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                 kcur = CK ? qk[u] : qf[u];
                 if (RHSA) bcur = qb[u];
                 if (!CK) ecur = qe[u];
-                if (CO) cs[(((F + 1) >> 1) & 3) * nc + l] = qc[u];
+                if (CO) {
+                    // coarse row (F+1)/2 into the 4-row ring; the ghost rows -1 and
+                    // nc (slots 3 and nc & 3) take the mirror of the edge row
+                    // (no flow) or 2 g - it (Dirichlet, Case I)
+                    const int Jl = (F + 1) >> 1;
+                    const T v = qc[u];
+                    cs[(Jl & 3) * nc + l] = (dns && Jl == nc) ? T(2) * cgN - v : v;
+                    if (F == 0) cs[3 * nc + l] = dns ? T(2) * cgS - v : v;
+                }
                 if (F + U < n) fetch(u, F + U);
             } else {
+                // past the top row: the north boundary faces (correction operator,
+                // Case I) stand in for the next row's south faces, and the ring row
+                // above row n-1 is cleared (its slot last held row n - RX, which no
+                // step from here on reads)
                 kcur = {T(0), T(0)};
+                if (F == n) {
+                    if (!CK && dns) kcur = ld2(A.f.fyn + size_t(s) * n + 2 * l);
+                    st2(xrow + 2 * l, T(0), T(0));
+                }
             }
             __syncthreads();
             // ---- 2. coarse-grid correction / FMG interpolation of row F (own cells)
             if (CO && F < n) {
-                const int J0 = F >> 1, J1 = min(max(J0 + ((F & 1) ? 1 : -1), 0), nc - 1);
+                // J1 = -1 and nc are the ghost rows of the ring; a corner takes the
+                // west/east rule applied to the ghost row's edge value
+                const int J0 = F >> 1, J1 = J0 + ((F & 1) ? 1 : -1);
                 const T *c0 = cs + (J0 & 3) * nc, *c1 = cs + (J1 & 3) * nc;
                 const T a0 = c0[l], a1 = c1[l];
                 const T w0 = first ? T(2) * cgW - a0 : c0[max(l - 1, 0)];
@@ -194,10 +218,10 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                         w_ = first ? T(2) * k0 : harm(kr[max(2 * l - 1, 0)], k0);
                         m_ = harm(k0, k1);
                         e_ = last ? T(2) * k1 : harm(k1, kr[min(2 * l + 2, n - 1)]);
-                        n0 = (r + 1 < n) ? harm(k0, kcur.a) : T(0);
-                        n1 = (r + 1 < n) ? harm(k1, kcur.b) : T(0);
-                        s0 = (r > 0) ? rn0[sp] : T(0);
-                        s1 = (r > 0) ? rn1[sp] : T(0);
+                        n0 = (r + 1 < n) ? harm(k0, kcur.a) : (dns ? T(2) * k0 : T(0));
+                        n1 = (r + 1 < n) ? harm(k1, kcur.b) : (dns ? T(2) * k1 : T(0));
+                        s0 = (r > 0) ? rn0[sp] : (dns ? T(2) * k0 : T(0));
+                        s1 = (r > 0) ? rn1[sp] : (dns ? T(2) * k1 : T(0));
                     } else {
                         w_ = kr[2 * l];
                         m_ = kr[2 * l + 1];
@@ -220,8 +244,18 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                         rb0[sr] = bprev.a;
                         rb1[sr] = bprev.b;
                     } else {
-                        rb0[sr] = first ? w_ * gW : T(0);
-                        rb1[sr] = last ? e_ * gE : T(0);
+                        T b0 = first ? w_ * gW : T(0);
+                        T b1 = last ? e_ * gE : T(0);
+                        if (dns && r == 0) {
+                            b0 += s0 * gS;
+                            b1 += s1 * gS;
+                        }
+                        if (dns && r == n - 1) {
+                            b0 += n0 * gN;
+                            b1 += n1 * gN;
+                        }
+                        rb0[sr] = b0;
+                        rb1[sr] = b1;
                     }
                 }
             }
@@ -284,7 +318,15 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
                     const V2<T> xv = ld2(row + 2 * l);
                     const T x0 = xv.a, x1 = xv.b;
                     st2(A.x + base + size_t(r) * n + 2 * l, x0, x1);
-                    if ((OUT & OUT_Q) && last) q += re[sr] * (x1 - gE);
+                    if (OUT & OUT_Q) {
+                        if (!dns) {
+                            if (last) q += re[sr] * (x1 - gE);
+                        } else if (r == (n >> 1) - 1 || r == (n >> 1)) {
+                            // centre cells n/2-1 and n/2: x1 of lane n/4-1, x0 of lane n/4
+                            if (l == (n >> 2) - 1) q += x1;
+                            else if (l == (n >> 2)) q += x0;
+                        }
+                    }
                 }
             }
         }
@@ -293,7 +335,17 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
         const T t = block_sum(rr, red);
         if (threadIdx.x == 0) A.rr[s] = double(t);
     }
-    if ((OUT & OUT_Q) && last) A.q[s] = double(q);
+    if (OUT & OUT_Q) {
+        if (!dns) {
+            if (last) A.q[s] = double(q);
+        } else {
+            // red[8], red[9] are not used by the residual reduction (at most 8 waves)
+            if (l == (n >> 2) - 1) red[8] = q;
+            if (l == (n >> 2)) red[9] = q;
+            __syncthreads();
+            if (l == 0) A.q[s] = double((red[8] + red[9]) * T(0.25));
+        }
+    }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -350,9 +402,10 @@ template int launch_march<float>(const MarchArgs<float> &, int, int, bool, int, 
 
 // ------------------------------------------------------------- face pyramid
 // Faces of the stage operator on n from K: west face of cell i (i = 0: 2K),
-// south face of row j (j = 0: no flow), east boundary face 2K.
+// south face of row j (j = 0: 2K in Case I, no flow in Case II), east and
+// north boundary faces 2K (north: 0 in Case II).
 template <typename T>
-__global__ void k_faces_from_k(int n, const T *__restrict__ K, Faces<T> out, int nc) {
+__global__ void k_faces_from_k(int n, const T *__restrict__ K, Faces<T> out, int nc, int all) {
     // coarse cell (I, J) of the n/2 grid from the four faces of the fine operator on it
     const int s = blockIdx.y;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -361,12 +414,17 @@ __global__ void k_faces_from_k(int n, const T *__restrict__ K, Faces<T> out, int
     const T *k = K + size_t(s) * n * n;
     auto kk = [&](int i, int j) { return k[size_t(j) * n + i]; };
     auto fxf = [&](int i, int j) -> T { return i == 0 ? T(2) * kk(0, j) : harm(kk(i - 1, j), kk(i, j)); };
-    auto fyf = [&](int i, int j) -> T { return j == 0 ? T(0) : harm(kk(i, j - 1), kk(i, j)); };
+    auto fyf = [&](int i, int j) -> T {
+        return j == 0 ? (all ? T(2) * kk(i, 0) : T(0)) : harm(kk(i, j - 1), kk(i, j));
+    };
     const size_t o = size_t(s) * nc * nc + size_t(J) * nc + I;
     out.fx[o] = T(0.5) * (fxf(2 * I, 2 * J) + fxf(2 * I, 2 * J + 1));
     out.fy[o] = T(0.5) * (fyf(2 * I, 2 * J) + fyf(2 * I + 1, 2 * J));
     if (I == nc - 1)
         out.fxe[size_t(s) * nc + J] = T(0.5) * (T(2) * kk(n - 1, 2 * J) + T(2) * kk(n - 1, 2 * J + 1));
+    if (J == nc - 1)
+        out.fyn[size_t(s) * nc + I] =
+            all ? T(0.5) * (T(2) * kk(2 * I, n - 1) + T(2) * kk(2 * I + 1, n - 1)) : T(0);
 }
 
 template <typename T>
@@ -381,13 +439,15 @@ __global__ void k_faces_coarsen(int n, Faces<T> in, Faces<T> out, int nc) {
     out.fy[o] = T(0.5) * (in.fy[fb + size_t(2 * J) * n + 2 * I] + in.fy[fb + size_t(2 * J) * n + 2 * I + 1]);
     if (I == nc - 1)
         out.fxe[size_t(s) * nc + J] = T(0.5) * (in.fxe[size_t(s) * n + 2 * J] + in.fxe[size_t(s) * n + 2 * J + 1]);
+    if (J == nc - 1)
+        out.fyn[size_t(s) * nc + I] = T(0.5) * (in.fyn[size_t(s) * n + 2 * I] + in.fyn[size_t(s) * n + 2 * I + 1]);
 }
 
 template <typename T>
-int launch_faces_from_k(int n, const T *K, Faces<T> out, int S, hipStream_t st) {
+int launch_faces_from_k(int n, const T *K, int all, Faces<T> out, int S, hipStream_t st) {
     const int nc = n / 2;
     dim3 block(256), grid((nc * nc + 255) / 256, S);
-    hipLaunchKernelGGL(k_faces_from_k<T>, grid, block, 0, st, n, K, out, nc);
+    hipLaunchKernelGGL(k_faces_from_k<T>, grid, block, 0, st, n, K, out, nc, all);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
@@ -399,8 +459,8 @@ int launch_faces_coarsen(int n, Faces<T> in, Faces<T> out, int S, hipStream_t st
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
-template int launch_faces_from_k<double>(int, const double *, Faces<double>, int, hipStream_t);
-template int launch_faces_from_k<float>(int, const float *, Faces<float>, int, hipStream_t);
+template int launch_faces_from_k<double>(int, const double *, int, Faces<double>, int, hipStream_t);
+template int launch_faces_from_k<float>(int, const float *, int, Faces<float>, int, hipStream_t);
 template int launch_faces_coarsen<double>(int, Faces<double>, Faces<double>, int, hipStream_t);
 template int launch_faces_coarsen<float>(int, Faces<float>, Faces<float>, int, hipStream_t);
 

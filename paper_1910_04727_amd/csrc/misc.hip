@@ -11,24 +11,35 @@ namespace {
 
 __device__ __forceinline__ double harm_d(double a, double b) { return 2.0 * a * b / (a + b); }
 
+// coarse value at (I, J) with ghosts: beyond the south / north side a mirror
+// (no flow) or 2 g - value (Dirichlet), then beyond the west / east side
+// 2 g - the edge value of that (possibly ghost) row
 template <typename T>
-__device__ __forceinline__ double ghost_d(const T *c, int nc, int I, int J, double gW, double gE) {
-    J = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
-    if (I < 0) return 2.0 * gW - double(c[J * nc]);
-    if (I >= nc) return 2.0 * gE - double(c[J * nc + nc - 1]);
-    return double(c[J * nc + I]);
+__device__ __forceinline__ double ghost_row_d(const T *c, int nc, int I, int J, const Bnd &g) {
+    if (J >= 0 && J < nc) return double(c[J * nc + I]);
+    const int Jc = J < 0 ? 0 : nc - 1;
+    return g.all ? 2.0 * (J < 0 ? g.s : g.n) - double(c[Jc * nc + I]) : double(c[Jc * nc + I]);
+}
+
+template <typename T>
+__device__ __forceinline__ double ghost_d(const T *c, int nc, int I, int J, const Bnd &g) {
+    if (I < 0) return 2.0 * g.w - ghost_row_d(c, nc, 0, J, g);
+    if (I >= nc) return 2.0 * g.e - ghost_row_d(c, nc, nc - 1, J, g);
+    return ghost_row_d(c, nc, I, J, g);
 }
 
 // Refinement pass, marching over rows (one workgroup per sample, one lane per
 // column): p <- p + e; r = b - A p in FP64 with the stage operator; r is
-// handed to the next FP32 cycles, ||r||^2 and the east outflow accumulate.
+// handed to the next FP32 cycles, ||r||^2 and the QoI accumulate (east
+// outflow in Case II, the centre pressure in Case I).
 __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
     const int n = A.n, i = threadIdx.x, s = blockIdx.x;
     if (A.active && A.active[s] == 0) return;
     extern __shared__ unsigned char smem_raw[];
     double *ps = reinterpret_cast<double *>(smem_raw);  // [3][n]
     double *ks = ps + 3 * n;                            // [3][n]
-    double *red = ks + 3 * n;                           // [16]
+    double *red = ks + 3 * n;                           // [18]: 16 wave partials, 2 QoI partials
+    const bool dns = A.g.all != 0;
     const size_t base = size_t(s) * n * n;
     double rr = 0.0, q = 0.0;
     double tn_prev = 0.0;
@@ -47,11 +58,13 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
             const double k0 = kr[i], x0 = pr[i];
             const double tw = (i > 0) ? harm_d(kr[i - 1], k0) : 2.0 * k0;
             const double te = (i < n - 1) ? harm_d(k0, kr[i + 1]) : 2.0 * k0;
-            const double tn = (r + 1 < n) ? harm_d(k0, ks[(F % 3) * n + i]) : 0.0;
-            const double ts = tn_prev;
+            const double tn = (r + 1 < n) ? harm_d(k0, ks[(F % 3) * n + i]) : (dns ? 2.0 * k0 : 0.0);
+            const double ts = (r > 0) ? tn_prev : (dns ? 2.0 * k0 : 0.0);
             double acc = 0.0;
-            if (i == 0) acc += tw * A.pW;
-            if (i == n - 1) acc += te * A.pE;
+            if (i == 0) acc += tw * A.g.w;
+            if (i == n - 1) acc += te * A.g.e;
+            if (dns && r == 0) acc += ts * A.g.s;
+            if (dns && r == n - 1) acc += tn * A.g.n;
             if (i > 0) acc += tw * pr[i - 1];
             if (i < n - 1) acc += te * pr[i + 1];
             if (r > 0) acc += ts * ps[((r + 2) % 3) * n + i];
@@ -60,7 +73,11 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
             rr += res * res;
             A.r32[base + size_t(r) * n + i] = float(res);
             if (A.e) A.p[base + size_t(r) * n + i] = x0;
-            if (i == n - 1) q += te * (x0 - A.pE);
+            if (!dns) {
+                if (i == n - 1) q += te * (x0 - A.g.e);
+            } else if ((r == (n >> 1) - 1 || r == (n >> 1)) && (i == (n >> 1) - 1 || i == (n >> 1))) {
+                q += x0;
+            }
             tn_prev = tn;
         }
     }
@@ -73,14 +90,22 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
         for (int w = 0; w < (n + 63) / 64; ++w) t += red[w];
         A.rr[s] = t;
     }
-    if (i == n - 1) A.q[s] = q;
+    if (!dns) {
+        if (i == n - 1) A.q[s] = q;
+    } else {
+        // centre columns n/2 - 1 and n/2, each summed over the two centre rows
+        if (i == (n >> 1) - 1) red[16] = q;
+        if (i == (n >> 1)) red[17] = q;
+        __syncthreads();
+        if (i == 0) A.q[s] = (red[16] + red[17]) * 0.25;
+    }
 }
 
 // One thread per coarse cell (I, J): its 2 x 2 fine cells from the 3 x 3
 // coarse neighbourhood (ghost values at the boundary), written as two
 // 16-byte row pairs.
 template <typename TS>
-__global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE) {
+__global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active, Bnd g) {
     const int s = blockIdx.y;
     if (active && active[s] == 0) return;
     const int nc = n / 2;
@@ -92,7 +117,7 @@ __global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active
 #pragma unroll
     for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-        for (int di = -1; di <= 1; ++di) v[dj + 1][di + 1] = ghost_d(x, nc, I + di, J + dj, pW, pE);
+        for (int di = -1; di <= 1; ++di) v[dj + 1][di + 1] = ghost_d(x, nc, I + di, J + dj, g);
     double *o = p + size_t(s) * n * n + size_t(2 * J) * n + 2 * I;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -107,17 +132,42 @@ __global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active
     }
 }
 
-// one workgroup per sample, lanes over the rows (column 0 and n-1 of each row)
+// one workgroup per sample, lanes over the rows (column 0 and n-1 of each row);
+// in Case I also over the columns of rows 0 and n-1, the corner cells taking
+// both of their boundary faces
 template <typename T>
-__global__ __launch_bounds__(256) void k_bnorm(int n, const T *K, double pW, double pE, double *bn) {
+__global__ __launch_bounds__(256) void k_bnorm(int n, const T *K, Bnd g, double *bn) {
     __shared__ double red[4];
     const int s = blockIdx.x;
     const T *k = K + size_t(s) * n * n;
+    auto kv = [&](int i, int j) { return 2.0 * double(k[size_t(j) * n + i]); };
     double acc = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const double bw = 2.0 * double(k[size_t(j) * n]) * pW;
-        const double be = 2.0 * double(k[size_t(j) * n + n - 1]) * pE;
-        acc += bw * bw + be * be;
+    if (!g.all) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const double bw = kv(0, j) * g.w;
+            const double be = kv(n - 1, j) * g.e;
+            acc += bw * bw + be * be;
+        }
+    } else {
+        for (int t = threadIdx.x; t < 4 * n; t += blockDim.x) {
+            // t < 2n: cell (i, 0) or (i, n-1); else the west / east cell of rows 1..n-2
+            int i, j;
+            if (t < 2 * n) {
+                i = t % n;
+                j = (t < n) ? 0 : n - 1;
+            } else {
+                const int u = t - 2 * n;
+                j = 1 + (u >> 1);
+                if (j > n - 2) continue;
+                i = (u & 1) ? n - 1 : 0;
+            }
+            double b = 0.0;
+            if (i == 0) b += kv(i, j) * g.w;
+            if (i == n - 1) b += kv(i, j) * g.e;
+            if (j == 0) b += kv(i, j) * g.s;
+            if (j == n - 1) b += kv(i, j) * g.n;
+            acc += b * b;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -242,30 +292,30 @@ int launch_ir(const IRArgs &a, int S, hipStream_t st) {
         return FMGMC_EINVAL;
     }
     if (S <= 0) return FMGMC_OK;
-    const size_t lds = (6 * size_t(a.n) + 16) * sizeof(double);
+    const size_t lds = (6 * size_t(a.n) + 18) * sizeof(double);
     hipLaunchKernelGGL(k_ir, dim3(S), dim3(a.n), lds, st, a);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
 template <typename TS>
-int launch_interp64(int n, const TS *xc, double *p, const int32_t *active, double pW, double pE, int S,
+int launch_interp64(int n, const TS *xc, double *p, const int32_t *active, const Bnd &g, int S,
                     hipStream_t st) {
     if (S <= 0) return FMGMC_OK;
     dim3 grid((n * n / 4 + 255) / 256, S);
-    hipLaunchKernelGGL(k_interp64<TS>, grid, dim3(256), 0, st, n, xc, p, active, pW, pE);
+    hipLaunchKernelGGL(k_interp64<TS>, grid, dim3(256), 0, st, n, xc, p, active, g);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
-template int launch_interp64<float>(int, const float *, double *, const int32_t *, double, double, int, hipStream_t);
-template int launch_interp64<double>(int, const double *, double *, const int32_t *, double, double, int, hipStream_t);
+template int launch_interp64<float>(int, const float *, double *, const int32_t *, const Bnd &, int, hipStream_t);
+template int launch_interp64<double>(int, const double *, double *, const int32_t *, const Bnd &, int, hipStream_t);
 
 template <typename T>
-int launch_bnorm(int n, const T *K, double pW, double pE, double *bn, int S, hipStream_t st) {
+int launch_bnorm(int n, const T *K, const Bnd &g, double *bn, int S, hipStream_t st) {
     if (S <= 0) return FMGMC_OK;
-    hipLaunchKernelGGL(k_bnorm<T>, dim3(S), dim3(256), 0, st, n, K, pW, pE, bn);
+    hipLaunchKernelGGL(k_bnorm<T>, dim3(S), dim3(256), 0, st, n, K, g, bn);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
-template int launch_bnorm<double>(int, const double *, double, double, double *, int, hipStream_t);
-template int launch_bnorm<float>(int, const float *, double, double, double *, int, hipStream_t);
+template int launch_bnorm<double>(int, const double *, const Bnd &, double *, int, hipStream_t);
+template int launch_bnorm<float>(int, const float *, const Bnd &, double *, int, hipStream_t);
 
 int launch_check(const CheckArgs &a, int S, hipStream_t st) {
     if (S <= 0) return FMGMC_OK;

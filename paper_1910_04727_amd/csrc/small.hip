@@ -6,7 +6,8 @@
 // FP64, applied as the explicit inverse of the 16 x 16 coarsest operator,
 // built once per batch from its Cholesky factor). With top == 0 the call is the
 // coarsest-grid direct solve itself (the first stage of full multigrid).
-// One 256-lane workgroup per sample.
+// One 256-lane workgroup per sample. Boundary conditions of Case II or Case I
+// (Table 1): a boundary face enters the diagonal and the right-hand side.
 #include "common.h"
 
 namespace fmgmc {
@@ -24,23 +25,39 @@ __device__ __forceinline__ T harm_s(T a, T b) {
 template <typename T>
 struct Lv {
     int n;
-    T *x, *b, *fx, *fy, *fxe, *id;
+    T *x, *b, *fx, *fy, *fxe, *fyn, *id;
 };
 
+// boundary values used by an interpolation (0 for a correction)
 template <typename T>
-__device__ __forceinline__ T ghost_at(const T *c, int nc, int I, int J, T gW, T gE) {
-    J = J < 0 ? 0 : (J >= nc ? nc - 1 : J);
-    if (I < 0) return T(2) * gW - c[J * nc];
-    if (I >= nc) return T(2) * gE - c[J * nc + nc - 1];
-    return c[J * nc + I];
+struct G4 {
+    T w, e, s, n;
+    bool all;
+};
+
+// value in coarse row J (a ghost row beyond the south / north side: a mirror
+// for no flow, 2 g - value for Dirichlet), then beyond the west / east side
+// 2 g - that row's edge value
+template <typename T>
+__device__ __forceinline__ T ghost_row(const T *c, int nc, int I, int J, const G4<T> &g) {
+    if (J >= 0 && J < nc) return c[J * nc + I];
+    const int Jc = J < 0 ? 0 : nc - 1;
+    return g.all ? T(2) * (J < 0 ? g.s : g.n) - c[Jc * nc + I] : c[Jc * nc + I];
 }
 
 template <typename T>
-__device__ __forceinline__ T interp_at(const T *c, int nc, int i, int j, T gW, T gE) {
+__device__ __forceinline__ T ghost_at(const T *c, int nc, int I, int J, const G4<T> &g) {
+    if (I < 0) return T(2) * g.w - ghost_row(c, nc, 0, J, g);
+    if (I >= nc) return T(2) * g.e - ghost_row(c, nc, nc - 1, J, g);
+    return ghost_row(c, nc, I, J, g);
+}
+
+template <typename T>
+__device__ __forceinline__ T interp_at(const T *c, int nc, int i, int j, const G4<T> &g) {
     const int I = i >> 1, J = j >> 1;
     const int di = (i & 1) ? 1 : -1, dj = (j & 1) ? 1 : -1;
-    return (T(9) * ghost_at(c, nc, I, J, gW, gE) + T(3) * ghost_at(c, nc, I + di, J, gW, gE) +
-            T(3) * ghost_at(c, nc, I, J + dj, gW, gE) + ghost_at(c, nc, I + di, J + dj, gW, gE)) /
+    return (T(9) * ghost_at(c, nc, I, J, g) + T(3) * ghost_at(c, nc, I + di, J, g) +
+            T(3) * ghost_at(c, nc, I, J + dj, g) + ghost_at(c, nc, I + di, J + dj, g)) /
            T(16);
 }
 
@@ -60,7 +77,7 @@ template <typename T>
 __device__ __forceinline__ T diag(const Lv<T> &L, int i, int j) {
     const int n = L.n, P = j * n + i;
     const T te = (i < n - 1) ? L.fx[P + 1] : L.fxe[j];
-    const T tn = (j < n - 1) ? L.fy[P + n] : T(0);
+    const T tn = (j < n - 1) ? L.fy[P + n] : L.fyn[i];
     return ((L.fx[P] + te) + L.fy[P]) + tn;
 }
 
@@ -101,10 +118,10 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     extern __shared__ unsigned char smem_raw[];
     T *const base = reinterpret_cast<T *>(smem_raw);
     const int top = A.top;
-    // level k arrays (x, b, fx, fy, id of n*n, then fxe of n), packed from level 0 up
+    // level k arrays (x, b, fx, fy, id of n*n, then fxe and fyn of n), packed from level 0 up
     auto lv = [&](int k) -> Lv<T> {
         T *p = base;
-        for (int j = 0; j < k; ++j) p += 5 * A.ns[j] * A.ns[j] + A.ns[j];
+        for (int j = 0; j < k; ++j) p += 5 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
         const int n = A.ns[k];
         Lv<T> L;
         L.n = n;
@@ -113,15 +130,18 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         L.fx = p; p += n * n;
         L.fy = p; p += n * n;
         L.id = p; p += n * n;
-        L.fxe = p;
+        L.fxe = p; p += n;
+        L.fyn = p;
         return L;
     };
     T *p = base;
-    for (int j = 0; j <= top; ++j) p += 5 * A.ns[j] * A.ns[j] + A.ns[j];
+    for (int j = 0; j <= top; ++j) p += 5 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
     double *Ls = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(p) + 7) & ~uintptr_t(7));
     const int N0 = A.ns[0] * A.ns[0];
     T *red = reinterpret_cast<T *>(Ls + N0 * N0);
-    const T gW = T(A.pW), gE = T(A.pE);
+    const bool dns = A.g.all != 0;
+    const G4<T> gsol{T(A.g.w), T(A.g.e), T(A.g.s), T(A.g.n), dns};
+    const G4<T> gzero{T(0), T(0), T(0), T(0), dns};
     // coefficients of every level
     for (int k = 0; k <= top; ++k) {
         const Lv<T> Lk = lv(k);
@@ -131,17 +151,21 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             for (int c = threadIdx.x; c < nn; c += blockDim.x) {
                 const int i = c % n, j = c / n;
                 Lk.fx[c] = i == 0 ? T(2) * K[c] : harm_s(K[c - 1], K[c]);
-                Lk.fy[c] = j == 0 ? T(0) : harm_s(K[c - n], K[c]);
+                Lk.fy[c] = j == 0 ? (dns ? T(2) * K[c] : T(0)) : harm_s(K[c - n], K[c]);
                 if (i == n - 1) Lk.fxe[j] = T(2) * K[c];
+                if (j == n - 1) Lk.fyn[i] = dns ? T(2) * K[c] : T(0);
             }
         } else {
             const T *fx = A.f[k].fx + size_t(s) * nn, *fy = A.f[k].fy + size_t(s) * nn;
-            const T *fe = A.f[k].fxe + size_t(s) * n;
+            const T *fe = A.f[k].fxe + size_t(s) * n, *fn = A.f[k].fyn + size_t(s) * n;
             for (int c = threadIdx.x; c < nn; c += blockDim.x) {
                 Lk.fx[c] = fx[c];
                 Lk.fy[c] = fy[c];
             }
-            for (int c = threadIdx.x; c < n; c += blockDim.x) Lk.fxe[c] = fe[c];
+            for (int c = threadIdx.x; c < n; c += blockDim.x) {
+                Lk.fxe[c] = fe[c];
+                Lk.fyn[c] = fn[c];
+            }
         }
     }
     for (int c = threadIdx.x; c < N0 * N0; c += blockDim.x) Ls[c] = A.chol[size_t(s) * N0 * N0 + c];
@@ -162,13 +186,15 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
                 Tp.b[c] = A.b[size_t(s) * nn + c];
             } else {
                 T b0 = T(0);
-                if (i == 0) b0 += Tp.fx[c] * gW;
-                if (i == n - 1) b0 += Tp.fxe[j] * gE;
+                if (i == 0) b0 += Tp.fx[c] * gsol.w;
+                if (i == n - 1) b0 += Tp.fxe[j] * gsol.e;
+                if (dns && j == 0) b0 += Tp.fy[c] * gsol.s;
+                if (dns && j == n - 1) b0 += Tp.fyn[i] * gsol.n;
                 Tp.b[c] = b0;
             }
             T xv = T(0);
             if (init == INIT_LOAD) xv = A.x[size_t(s) * nn + c];
-            else if (init == INIT_INTERP) xv = interp_at(A.xc + size_t(s) * (nn / 4), n / 2, i, j, gW, gE);
+            else if (init == INIT_INTERP) xv = interp_at(A.xc + size_t(s) * (nn / 4), n / 2, i, j, gsol);
             Tp.x[c] = xv;
         }
     }
@@ -220,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
             const int n = Lk.n, nc = n / 2;
             for (int c = threadIdx.x; c < n * n; c += blockDim.x)
-                Lk.x[c] += interp_at(Lc.x, nc, c % n, c / n, T(0), T(0));
+                Lk.x[c] += interp_at(Lc.x, nc, c % n, c / n, gzero);
             __syncthreads();
             smooth(Lk, A.nu2);
             if (k == top) break;
@@ -250,7 +276,13 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     }
     if ((out & OUT_Q) && threadIdx.x == 0) {
         T q = T(0);
-        for (int j = 0; j < n; ++j) q += Tp.fxe[j] * (Tp.x[j * n + n - 1] - gE);
+        if (dns) {
+            const int m = n >> 1;  // centre cells m-1, m (n >= 4)
+            q = ((Tp.x[(m - 1) * n + m - 1] + Tp.x[m * n + m - 1]) + (Tp.x[(m - 1) * n + m] + Tp.x[m * n + m])) *
+                T(0.25);
+        } else {
+            for (int j = 0; j < n; ++j) q += Tp.fxe[j] * (Tp.x[j * n + n - 1] - gsol.e);
+        }
         A.q[s] = double(q);
     }
 }
@@ -265,7 +297,7 @@ int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out
     }
     if (S <= 0) return FMGMC_OK;
     size_t words = 0;
-    for (int k = 0; k <= a.top; ++k) words += 5 * size_t(a.ns[k]) * a.ns[k] + a.ns[k];
+    for (int k = 0; k <= a.top; ++k) words += 5 * size_t(a.ns[k]) * a.ns[k] + 2 * size_t(a.ns[k]);
     const int N0 = a.ns[0] * a.ns[0];
     size_t bytes = words * sizeof(T);
     bytes = (bytes + 7) & ~size_t(7);
@@ -283,7 +315,7 @@ template int launch_small<float>(const SmallArgs<float> &, int, int, bool, int, 
 // below the diagonal), the columns of L^{-1} by forward substitution (one
 // lane per column), then A^{-1} = L^{-T} L^{-1} (lanes over the entries).
 template <typename T>
-__global__ __launch_bounds__(64) void k_chol(int n0, const T *K, Faces<T> f, bool from_k, double *Lout) {
+__global__ __launch_bounds__(64) void k_chol(int n0, const T *K, Faces<T> f, bool from_k, int all, double *Lout) {
     __shared__ double L[16 * 16];
     __shared__ double Li[16 * 16];
     const int s = blockIdx.x, t = threadIdx.x;
@@ -299,12 +331,14 @@ __global__ __launch_bounds__(64) void k_chol(int n0, const T *K, Faces<T> f, boo
         if (from_k) return 2.0 * double(K[size_t(s) * N + j * n0 + n0 - 1]);
         return double(f.fxe[size_t(s) * n0 + j]);
     };
-    auto fyv = [&](int i, int j) -> double {
-        if (j == 0) return 0.0;
+    auto fyv = [&](int i, int j) -> double {  // south face of cell (i, j), j = n0: north boundary
         if (from_k) {
             const T *k = K + size_t(s) * N;
+            if (j == 0) return all ? 2.0 * double(k[i]) : 0.0;
+            if (j == n0) return all ? 2.0 * double(k[(n0 - 1) * n0 + i]) : 0.0;
             return double(harm_s(k[(j - 1) * n0 + i], k[j * n0 + i]));
         }
+        if (j == n0) return double(f.fyn[size_t(s) * n0 + i]);
         return double(f.fy[size_t(s) * N + j * n0 + i]);
     };
     for (int e = t; e < N * N; e += 64) L[e] = 0.0;
@@ -312,7 +346,7 @@ __global__ __launch_bounds__(64) void k_chol(int n0, const T *K, Faces<T> f, boo
     if (t < N) {
         const int P = t, i = P % n0, j = P / n0;
         const double w = fxv(i, j), e = (i < n0 - 1) ? fxv(i + 1, j) : fxe(j);
-        const double so = fyv(i, j), no = (j < n0 - 1) ? fyv(i, j + 1) : 0.0;
+        const double so = fyv(i, j), no = fyv(i, j + 1);
         L[P * N + P] = ((w + e) + so) + no;
         if (i > 0) L[P * N + P - 1] = -w;
         if (j > 0) L[P * N + P - n0] = -so;
@@ -351,17 +385,17 @@ __global__ __launch_bounds__(64) void k_chol(int n0, const T *K, Faces<T> f, boo
 }
 
 template <typename T>
-int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, double *L, int S, hipStream_t st) {
+int launch_chol(int n0, const T *K, Faces<T> f, bool from_k, int all, double *L, int S, hipStream_t st) {
     if (n0 * n0 > 16) {
         set_error("launch_chol: coarsest grid too large");
         return FMGMC_EINVAL;
     }
     if (S <= 0) return FMGMC_OK;
-    hipLaunchKernelGGL(k_chol<T>, dim3(S), dim3(64), 0, st, n0, K, f, from_k, L);
+    hipLaunchKernelGGL(k_chol<T>, dim3(S), dim3(64), 0, st, n0, K, f, from_k, all, L);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
-template int launch_chol<double>(int, const double *, Faces<double>, bool, double *, int, hipStream_t);
-template int launch_chol<float>(int, const float *, Faces<float>, bool, double *, int, hipStream_t);
+template int launch_chol<double>(int, const double *, Faces<double>, bool, int, double *, int, hipStream_t);
+template int launch_chol<float>(int, const float *, Faces<float>, bool, int, double *, int, hipStream_t);
 
 }  // namespace fmgmc

@@ -26,7 +26,15 @@ class Field(C.Structure):
 
 class Hier(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n0", C.c_int32), ("n_coarsest", C.c_int32),
-                ("reserved", C.c_int32), ("p_west", C.c_double), ("p_east", C.c_double)]
+                ("boundary", C.c_int32), ("p_west", C.c_double), ("p_east", C.c_double),
+                ("p_south", C.c_double), ("p_north", C.c_double)]
+
+
+# Table 1: case 2 (Dirichlet west/east, no flow south/north, east outflow) and
+# case 1 (Dirichlet on every side, centre pressure). Default boundary values
+# (west, east, south, north): the paper's 100/0 and 100/0/10/50 scaled by 1/100
+# (the problem is linear in them).
+BOUNDARY_DEFAULTS = {2: (1.0, 0.0, 0.0, 0.0), 1: (1.0, 0.0, 0.1, 0.5)}
 
 
 class Opts(C.Structure):
@@ -141,9 +149,14 @@ class Context:
 
     def __init__(self, sigma2, corr_len, n_modes, n_levels, n0, solver="fp64", kl_prec="fp64",
                  nu1=2, nu2=2, max_cycles=50, inner_cycles=1, max_batch=0, rel_tol=1e-10,
-                 p_west=1.0, p_east=0.0, device=0, w_max_n=64, inner_first=0, separate_coarse=False):
+                 p_west=None, p_east=None, device=0, w_max_n=64, inner_first=0, separate_coarse=False,
+                 case=2, p_south=None, p_north=None):
+        if case not in BOUNDARY_DEFAULTS:
+            raise ValueError("case must be 1 or 2 (Table 1)")
+        g = [d if v is None else float(v) for d, v in zip(BOUNDARY_DEFAULTS[case], (p_west, p_east, p_south, p_north))]
+        self.case = case
         self.field = Field(sigma2, corr_len, n_modes, 0)
-        self.hier = Hier(n_levels, n0, 4, 0, p_west, p_east)
+        self.hier = Hier(n_levels, n0, 4, 1 if case == 1 else 0, *g)
         self.opts = Opts(SOLVERS[solver], KL_PREC[kl_prec], nu1, nu2, max_cycles, inner_cycles,
                          max_batch, w_max_n, rel_tol, inner_first, 1 if separate_coarse else 0)
         self.n_modes = n_modes
