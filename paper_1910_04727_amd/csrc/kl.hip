@@ -200,54 +200,52 @@ __global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
 // instead of 2 M n^2, and the pass is bound by writing the coefficient pyramid.
 // Workgroup: one sample and a band of 64 grid rows; T for the band is formed
 // once (FP64 MFMA), then each 64-cell x-tile of the band is one FP64 MFMA
-// contraction over a. LDS strides keep the operand reads conflict-free
-// (A-type reads: stride = 2 mod 4 doubles per pair of rows; T: 80).
+// contraction over a. The 1-D eigenfunction values (a [kdim][n] table that
+// stays in L2) are read as MFMA operands straight from global memory, so the
+// x-tiles need no LDS staging and no barrier: each wave streams through its
+// tiles and the matrix cores, the exp and the pyramid stores of different
+// waves overlap. LDS holds only C_s, then T (the same space, 80-double rows,
+// conflict-free operand reads): 30 KB at 48 modes per axis.
 constexpr int SB = 64;
 constexpr int TSTR = SB + 16;
 
 template <int AP>
 __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
     constexpr int CSd = AP + 2;
+    static_assert(CSd <= TSTR, "C_s must fit in the space of T");
     extern __shared__ double sm[];
     double *Cm = sm;                 // [AP][CSd]   C_s[a][b]
-    double *P = Cm + AP * CSd;       // [SB][CSd]   phi_b(y_j) of the band, then phi_a(x_i) of an x-tile
-    double *Tt = P + SB * CSd;       // [AP][TSTR]  T_s[a][j] of the band
+    double *Tt = sm;                 // [AP][TSTR]  T_s[a][j] of the band (replaces C_s)
     const int n = A.n, s = blockIdx.y, j0 = blockIdx.x * SB, KD = A.kdim;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     if (s >= S) return;
     for (int e = t; e < AP * CSd; e += 256) Cm[e] = 0.0;
-    for (int e = t; e < SB * CSd; e += 256) {
-        const int jj = e / CSd, b = e % CSd;
-        P[e] = (b < KD) ? A.phi[size_t(b) * n + j0 + jj] : 0.0;
-    }
     __syncthreads();
     for (int m = t; m < A.M; m += 256) Cm[A.ma[m] * CSd + A.mb[m]] = A.xi[size_t(s) * A.M + m] * A.sqrtlam[m];
     __syncthreads();
+    // phi_k(s_i) for k < KD (zero for the padding modes k >= KD)
+    auto phi = [&](int k, int i) -> double { return k < KD ? A.phi[size_t(k) * n + i] : 0.0; };
     {   // T[a][j] = sum_b C[a][b] phi_b(y_j): wave w owns the j columns 16w .. 16w+15
         d4 acc[AP / 16];
 #pragma unroll
         for (int q = 0; q < AP / 16; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
         for (int kk = 0; kk < AP / 4; ++kk) {
-            const double bv = P[(16 * w + (l & 15)) * CSd + 4 * kk + (l >> 4)];
+            const double bv = phi(4 * kk + (l >> 4), j0 + 16 * w + (l & 15));
 #pragma unroll
             for (int q = 0; q < AP / 16; ++q) {
                 const double av = Cm[(16 * q + (l & 15)) * CSd + 4 * kk + (l >> 4)];
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
             }
         }
+        __syncthreads();  // every wave's reads of C_s are done before T overwrites it
 #pragma unroll
         for (int q = 0; q < AP / 16; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v) Tt[(16 * q + 4 * v + (l >> 4)) * TSTR + 16 * w + (l & 15)] = acc[q][v];
     }
+    __syncthreads();
     for (int i0 = 0; i0 < n; i0 += SB) {
-        __syncthreads();  // T complete / previous tile's reads of P done
-        for (int e = t; e < SB * CSd; e += 256) {
-            const int ii = e / CSd, a = e % CSd;
-            P[e] = (a < KD) ? A.phi[size_t(a) * n + i0 + ii] : 0.0;
-        }
-        __syncthreads();
         // g[j][i] = sum_a T[a][j] phi_a(x_i): wave w owns rows j 16w .., four 16-cell i-tiles
         d4 acc[4];
 #pragma unroll
@@ -257,7 +255,7 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
             const double av = Tt[(4 * kk + (l >> 4)) * TSTR + 16 * w + (l & 15)];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double bv = P[(16 * q + (l & 15)) * CSd + 4 * kk + (l >> 4)];
+                const double bv = phi(4 * kk + (l >> 4), i0 + 16 * q + (l & 15));
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
             }
         }
@@ -272,7 +270,7 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
 
 template <int AP>
 size_t sep_lds() {
-    return size_t(AP * (AP + 2) + SB * (AP + 2) + AP * TSTR) * sizeof(double);
+    return size_t(AP) * TSTR * sizeof(double);  // C_s ([AP][AP+2]) and T ([AP][TSTR]) share it
 }
 
 // BF16 inputs, FP32 accumulation: v_mfma_f32_16x16x32_bf16. Lane l holds

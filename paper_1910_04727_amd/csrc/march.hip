@@ -149,185 +149,43 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     T rprev = T(0), rr = T(0), q = T(0);
 
     const int LAST = n - 1 + NH + (RES ? 1 : 0);
-    for (int F0 = 0; F0 <= LAST; F0 += U) {
+    // Row steps (march_step.inc). FP32: range-checked steps at both ends and
+    // straight-line steps in between, so the prefetches of the queue are never
+    // conditional and no wait for outstanding loads is forced at a merge; the
+    // step is a lambda there (that keeps these kernels within 128 registers).
+    // FP64: checked steps only, inline in the loop (its register rings leave
+    // no room for a second copy of the step, and behind a lambda the compiler
+    // kept one of its queues in scratch memory).
+    if constexpr (sizeof(T) == 4) {
+        auto step = [&](const int F, const int u, auto chk) {
+            constexpr bool C = decltype(chk)::value;
+#include "march_step.inc"
+        };
+        const int lo = ((NH + 1 + U - 1) / U) * U;       // first unchecked step
+        const int hi = max(lo, ((n - U) / U) * U);         // first checked step after them
+        int F0 = 0;
+        for (; F0 < lo; F0 += U) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int F = F0 + u;
-            if (F > LAST) break;
-            T *xrow = xs + (F & (RX - 1)) * XS + 2;
-            // ---- 1. take row F from the queue into LDS, refill the slot with row F + U
-            kprev = kcur;
-            bprev = bcur;
-            eprev = ecur;
-            V2<T> xraw{T(0), T(0)};
-            if (F < n) {
-                if (LX) xraw = qx[u];
-                if (LX) st2(xrow + 2 * l, xraw.a, xraw.b);
-                else if (INIT == INIT_ZERO) st2(xrow + 2 * l, T(0), T(0));
-                st2(ks + (F & 3) * n + 2 * l, qk[u].a, qk[u].b);
-                kcur = CK ? qk[u] : qf[u];
-                if (RHSA) bcur = qb[u];
-                if (!CK) ecur = qe[u];
-                if (CO) {
-                    // coarse row (F+1)/2 into the 4-row ring; the ghost rows -1 and
-                    // nc (slots 3 and nc & 3) take the mirror of the edge row
-                    // (no flow) or 2 g - it (Dirichlet, Case I)
-                    const int Jl = (F + 1) >> 1;
-                    const T v = qc[u];
-                    cs[(Jl & 3) * nc + l] = (dns && Jl == nc) ? T(2) * cgN - v : v;
-                    if (F == 0) cs[3 * nc + l] = dns ? T(2) * cgS - v : v;
-                }
-                if (F + U < n) fetch(u, F + U);
-            } else {
-                // past the top row: the north boundary faces (correction operator,
-                // Case I) stand in for the next row's south faces, and the ring row
-                // above row n-1 is cleared (its slot last held row n - RX, which no
-                // step from here on reads)
-                kcur = {T(0), T(0)};
-                if (F == n) {
-                    if (!CK && dns) kcur = ld2(A.f.fyn + size_t(s) * n + 2 * l);
-                    st2(xrow + 2 * l, T(0), T(0));
-                }
-            }
-            __syncthreads();
-            // ---- 2. coarse-grid correction / FMG interpolation of row F (own cells)
-            if (CO && F < n) {
-                // J1 = -1 and nc are the ghost rows of the ring; a corner takes the
-                // west/east rule applied to the ghost row's edge value
-                const int J0 = F >> 1, J1 = J0 + ((F & 1) ? 1 : -1);
-                const T *c0 = cs + (J0 & 3) * nc, *c1 = cs + (J1 & 3) * nc;
-                const T a0 = c0[l], a1 = c1[l];
-                const T w0 = first ? T(2) * cgW - a0 : c0[max(l - 1, 0)];
-                const T w1 = first ? T(2) * cgW - a1 : c1[max(l - 1, 0)];
-                const T e0 = last ? T(2) * cgE - a0 : c0[min(l + 1, nc - 1)];
-                const T e1 = last ? T(2) * cgE - a1 : c1[min(l + 1, nc - 1)];
-                const T p0 = (T(9) * a0 + T(3) * w0 + T(3) * a1 + w1) / T(16);
-                const T p1 = (T(9) * a0 + T(3) * e0 + T(3) * a1 + e1) / T(16);
-                if (INIT == INIT_PROLONG) st2(xrow + 2 * l, xraw.a + p0, xraw.b + p1);
-                else st2(xrow + 2 * l, p0, p1);
-            }
-            // ---- 3. coefficients of row r = F - 1
-            {
-                const int r = F - 1;
-                const int sr = (u + U - 1) % U, sp = (u + U - 2) % U;
-                if (r >= 0 && r < n) {
-                    const T *kr = ks + (r & 3) * n;
-                    T w_, m_, e_, s0, s1, n0, n1;
-                    if (CK) {
-                        const T k0 = kprev.a, k1 = kprev.b;
-                        w_ = first ? T(2) * k0 : harm(kr[max(2 * l - 1, 0)], k0);
-                        m_ = harm(k0, k1);
-                        e_ = last ? T(2) * k1 : harm(k1, kr[min(2 * l + 2, n - 1)]);
-                        n0 = (r + 1 < n) ? harm(k0, kcur.a) : (dns ? T(2) * k0 : T(0));
-                        n1 = (r + 1 < n) ? harm(k1, kcur.b) : (dns ? T(2) * k1 : T(0));
-                        s0 = (r > 0) ? rn0[sp] : (dns ? T(2) * k0 : T(0));
-                        s1 = (r > 0) ? rn1[sp] : (dns ? T(2) * k1 : T(0));
-                    } else {
-                        w_ = kr[2 * l];
-                        m_ = kr[2 * l + 1];
-                        e_ = last ? eprev : kr[min(2 * l + 2, n - 1)];
-                        s0 = kprev.a;
-                        s1 = kprev.b;
-                        n0 = kcur.a;
-                        n1 = kcur.b;
-                    }
-                    rw[sr] = w_;
-                    rm[sr] = m_;
-                    re[sr] = e_;
-                    rs0[sr] = s0;
-                    rs1[sr] = s1;
-                    rn0[sr] = n0;
-                    rn1[sr] = n1;
-                    ri0[sr] = rcp_(((w_ + m_) + s0) + n0);
-                    ri1[sr] = rcp_(((m_ + e_) + s1) + n1);
-                    if (RHSA) {
-                        rb0[sr] = bprev.a;
-                        rb1[sr] = bprev.b;
-                    } else {
-                        T b0 = first ? w_ * gW : T(0);
-                        T b1 = last ? e_ * gE : T(0);
-                        if (dns && r == 0) {
-                            b0 += s0 * gS;
-                            b1 += s1 * gS;
-                        }
-                        if (dns && r == n - 1) {
-                            b0 += n0 * gN;
-                            b1 += n1 * gN;
-                        }
-                        rb0[sr] = b0;
-                        rb1[sr] = b1;
-                    }
-                }
-            }
-            // ---- 4. half-sweeps: sweep t on row F - t, colour (t-1) & 1
+            for (int u = 0; u < U; ++u)
+                if (F0 + u <= LAST) step(F0 + u, u, std::true_type{});
+        }
+        for (; F0 < hi; F0 += U) {
 #pragma unroll
-            for (int t = 1; t <= NH; ++t) {
-                const int r = F - t;
-                if (r >= 0 && r < n) {
-                    const int sr = (u + 2 * U - t) % U;
-                    T *row = xs + (r & (RX - 1)) * XS + 2;
-                    const T *up = xs + ((r + 1) & (RX - 1)) * XS + 2;
-                    const T *dn = xs + ((r - 1) & (RX - 1)) * XS + 2;
-                    // cell pairs are read and written whole: consecutive lanes touch
-                    // consecutive 2-cell words, which keeps the LDS accesses
-                    // conflict-free; the partner cell is written back unchanged
-                    const V2<T> own = ld2(row + 2 * l), vd = ld2(dn + 2 * l), vu = ld2(up + 2 * l);
-                    if (((t - 1 + r) & 1) == 0) {  // this lane's red/black cell is column 2l
-                        const T west = ld2(row + 2 * l - 2).b;
-                        const T v = (((rb0[sr] + rw[sr] * west) + rm[sr] * own.b) + rs0[sr] * vd.a +
-                                     rn0[sr] * vu.a) * ri0[sr];
-                        st2(row + 2 * l, v, own.b);
-                    } else {                        // column 2l + 1
-                        const T east = ld2(row + 2 * l + 2).a;
-                        const T v = (((rb1[sr] + rm[sr] * own.a) + re[sr] * east) + rs1[sr] * vd.b +
-                                     rn1[sr] * vu.b) * ri1[sr];
-                        st2(row + 2 * l, own.a, v);
-                    }
-                }
-            }
-            // ---- 5. residual of row r = F - NH - 1
-            if (RES) {
-                const int r = F - NH - 1;
-                if (r >= 0 && r < n) {
-                    const int sr = (u + 2 * U - NH - 1) % U;
-                    const T *row = xs + (r & (RX - 1)) * XS + 2;
-                    const T *up = xs + ((r + 1) & (RX - 1)) * XS + 2;
-                    const T *dn = xs + ((r - 1) & (RX - 1)) * XS + 2;
-                    const V2<T> own = ld2(row + 2 * l), vd = ld2(dn + 2 * l), vu = ld2(up + 2 * l);
-                    const T x0 = own.a, x1 = own.b;
-                    const T west = ld2(row + 2 * l - 2).b, east = ld2(row + 2 * l + 2).a;
-                    const T d0 = ((rw[sr] + rm[sr]) + rs0[sr]) + rn0[sr];
-                    const T d1 = ((rm[sr] + re[sr]) + rs1[sr]) + rn1[sr];
-                    const T res0 = (((rb0[sr] + rw[sr] * west) + rm[sr] * x1) + rs0[sr] * vd.a + rn0[sr] * vu.a) -
-                                   d0 * x0;
-                    const T res1 = (((rb1[sr] + rm[sr] * x0) + re[sr] * east) + rs1[sr] * vd.b + rn1[sr] * vu.b) -
-                                   d1 * x1;
-                    if (OUT & OUT_RR) rr += res0 * res0 + res1 * res1;
-                    if (OUT & OUT_RESTRICT) {
-                        if (r & 1) A.bc[cbase + size_t(r >> 1) * nc + l] = ((rprev + res0) + res1);
-                        else rprev = res0 + res1;
-                    }
-                }
-            }
-            // ---- 6. write back the finished row F - NH
-            {
-                const int r = F - NH;
-                if (r >= 0 && r < n) {
-                    const int sr = (u + 2 * U - NH) % U;
-                    const T *row = xs + (r & (RX - 1)) * XS + 2;
-                    const V2<T> xv = ld2(row + 2 * l);
-                    const T x0 = xv.a, x1 = xv.b;
-                    st2(A.x + base + size_t(r) * n + 2 * l, x0, x1);
-                    if (OUT & OUT_Q) {
-                        if (!dns) {
-                            if (last) q += re[sr] * (x1 - gE);
-                        } else if (r == (n >> 1) - 1 || r == (n >> 1)) {
-                            // centre cells n/2-1 and n/2: x1 of lane n/4-1, x0 of lane n/4
-                            if (l == (n >> 2) - 1) q += x1;
-                            else if (l == (n >> 2)) q += x0;
-                        }
-                    }
-                }
+            for (int u = 0; u < U; ++u) step(F0 + u, u, std::false_type{});
+        }
+        for (; F0 <= LAST; F0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (F0 + u <= LAST) step(F0 + u, u, std::true_type{});
+        }
+    } else {
+        for (int F0 = 0; F0 <= LAST; F0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int F = F0 + u;
+                if (F > LAST) break;
+                constexpr bool C = true;
+#include "march_step.inc"
             }
         }
     }
