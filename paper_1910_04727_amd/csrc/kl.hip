@@ -199,19 +199,36 @@ __global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
 // With A 1-D modes per axis (A <= 64) this is 2 (A + n) A n flops per sample
 // instead of 2 M n^2, and the pass is bound by writing the coefficient pyramid.
 // Workgroup: one sample and a band of 64 grid rows; T for the band is formed
-// once (FP64 MFMA), then each 64-cell x-tile of the band is one FP64 MFMA
-// contraction over a. The 1-D eigenfunction values (a [kdim][n] table that
-// stays in L2) are read as MFMA operands straight from global memory, so the
-// x-tiles need no LDS staging and no barrier: each wave streams through its
-// tiles and the matrix cores, the exp and the pyramid stores of different
-// waves overlap. LDS holds only C_s, then T (the same space, 80-double rows,
-// conflict-free operand reads): 30 KB at 48 modes per axis.
+// once (FP64 MFMA). Then each wave takes its own 16-column x-tiles (every 4th)
+// over all 64 rows: g[j][i] = sum_a T[a][j] phi_a(x_i), four 16 x 16 FP64 MFMA
+// outputs per tile, A operands (T) from LDS, B operands phi_a(x_i) from the
+// L2-resident [kdim][n] table; no two waves load the same operand, and no
+// barrier separates the tiles. LDS holds only C_s, then T
+// (the same space, 80-double rows, conflict-free operand reads): 30 KB at 48
+// modes per axis. The epilogue (exp, the pyramid) writes 16 values per lane
+// per tile; the parity of a lane's rows and columns is fixed, so the coarse
+// levels are taken only by the lanes that own even cells.
 constexpr int SB = 64;
 constexpr int TSTR = SB + 16;
+
+// levels >= 1 of the pyramid for one fine cell (i, j) with both indices even
+__device__ __forceinline__ void store_coarse(const KLArgs &A, int s, int i, int j, double kv) {
+    int nl = A.n, ii = i, jj = j;
+    for (int k = 1; k < A.nlev; ++k) {
+        ii >>= 1;
+        jj >>= 1;
+        nl >>= 1;
+        const size_t o = size_t(s) * nl * nl + size_t(jj) * nl + ii;
+        if (A.K64[k]) A.K64[k][o] = kv;
+        if (A.K32[k]) A.K32[k][o] = float(kv);
+        if ((ii & 1) || (jj & 1)) break;
+    }
+}
 
 template <int AP>
 __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
     constexpr int CSd = AP + 2;
+    constexpr int KK = AP / 4;
     static_assert(CSd <= TSTR, "C_s must fit in the space of T");
     extern __shared__ double sm[];
     double *Cm = sm;                 // [AP][CSd]   C_s[a][b]
@@ -230,7 +247,7 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
 #pragma unroll
         for (int q = 0; q < AP / 16; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int kk = 0; kk < AP / 4; ++kk) {
+        for (int kk = 0; kk < KK; ++kk) {
             const double bv = phi(4 * kk + (l >> 4), j0 + 16 * w + (l & 15));
 #pragma unroll
             for (int q = 0; q < AP / 16; ++q) {
@@ -245,26 +262,35 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
             for (int v = 0; v < 4; ++v) Tt[(16 * q + 4 * v + (l >> 4)) * TSTR + 16 * w + (l & 15)] = acc[q][v];
     }
     __syncthreads();
-    for (int i0 = 0; i0 < n; i0 += SB) {
-        // g[j][i] = sum_a T[a][j] phi_a(x_i): wave w owns rows j 16w .., four 16-cell i-tiles
+    // lane l holds output rows 4v + l/16 (+16g) and column l%16 of a tile
+    const int r0 = l >> 4, c0 = l & 15;
+    const bool even = ((r0 | c0) & 1) == 0;
+    for (int i0 = 16 * w; i0 < n; i0 += 64) {
         d4 acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int g = 0; g < 4; ++g) acc[g] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int kk = 0; kk < AP / 4; ++kk) {
-            const double av = Tt[(4 * kk + (l >> 4)) * TSTR + 16 * w + (l & 15)];
+        for (int kk = 0; kk < KK; ++kk) {
+            const double bv = phi(4 * kk + r0, i0 + c0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double bv = phi(4 * kk + (l >> 4), i0 + 16 * q + (l & 15));
-                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+            for (int g = 0; g < 4; ++g) {
+                const double av = Tt[(4 * kk + r0) * TSTR + 16 * g + c0];
+                acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[g], 0, 0, 0);
             }
         }
+        const int i = i0 + c0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                store_pyramid(A, S, s, (j0 + 16 * w + 4 * v + (l >> 4)) * n + i0 + 16 * q + (l & 15), acc[q][v],
-                              false);
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll 1
+            for (int v = 0; v < 4; ++v) {
+                const int j = j0 + 16 * g + 4 * v + r0;
+                const double kv = exp(acc[g][v]);
+                const size_t o = size_t(s) * n * n + size_t(j) * n + i;
+                if (A.K64[0]) A.K64[0][o] = kv;
+                if (A.K32[0]) A.K32[0][o] = float(kv);
+                if (even) store_coarse(A, s, i, j, kv);
+            }
+        }
     }
 }
 
