@@ -2,6 +2,7 @@
 // FP64, right-hand-side norms, per-sample convergence bookkeeping and the
 // compensated estimator reductions (Section 2.1 Eqs. (3)-(5), Section 2.4).
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
@@ -43,32 +44,49 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
     const size_t base = size_t(s) * n * n;
     double rr = 0.0, q = 0.0;
     double tn_prev = 0.0;
-    for (int F = 0; F <= n; ++F) {
-        if (F < n) {
-            const size_t idx = base + size_t(F) * n + i;
-            double pv = A.p[idx];
-            if (A.e) pv += double(A.e[idx]);
+    // rows F + 1 .. F + D are in flight in a register queue (slot = row % D)
+    constexpr int D = 4;
+    double qp[D], qk[D];
+    float qe[D];
+    auto fetch = [&](int slot, int row) {
+        const size_t idx = base + size_t(row) * n + i;
+        qp[slot] = A.p[idx];
+        if (A.e) qe[slot] = A.e[idx];
+        qk[slot] = A.K[idx];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (d < n) fetch(d, d);
+    // step F: row F enters the LDS ring, the residual of row F - 1 is formed. With
+    // C (checked) the row indices are range-tested; without, valid for 2 <= F and
+    // F + D < n, the step is straight-line code and no prefetch is conditional.
+    auto step = [&](const int F, const int u, auto chk) {
+        constexpr bool C = decltype(chk)::value;
+        if (!C || F < n) {
+            double pv = qp[u];
+            if (A.e) pv += double(qe[u]);
             ps[(F % 3) * n + i] = pv;
-            ks[(F % 3) * n + i] = A.K[idx];
+            ks[(F % 3) * n + i] = qk[u];
+            if (!C || F + D < n) fetch(u, F + D);
         }
         __syncthreads();
         const int r = F - 1;
-        if (r >= 0) {
+        if (!C || r >= 0) {
             const double *kr = ks + (r % 3) * n, *pr = ps + (r % 3) * n;
             const double k0 = kr[i], x0 = pr[i];
             const double tw = (i > 0) ? harm_d(kr[i - 1], k0) : 2.0 * k0;
             const double te = (i < n - 1) ? harm_d(k0, kr[i + 1]) : 2.0 * k0;
-            const double tn = (r + 1 < n) ? harm_d(k0, ks[(F % 3) * n + i]) : (dns ? 2.0 * k0 : 0.0);
-            const double ts = (r > 0) ? tn_prev : (dns ? 2.0 * k0 : 0.0);
+            const double tn = (!C || r + 1 < n) ? harm_d(k0, ks[(F % 3) * n + i]) : (dns ? 2.0 * k0 : 0.0);
+            const double ts = (!C || r > 0) ? tn_prev : (dns ? 2.0 * k0 : 0.0);
             double acc = 0.0;
             if (i == 0) acc += tw * A.g.w;
             if (i == n - 1) acc += te * A.g.e;
-            if (dns && r == 0) acc += ts * A.g.s;
-            if (dns && r == n - 1) acc += tn * A.g.n;
+            if (C && dns && r == 0) acc += ts * A.g.s;
+            if (C && dns && r == n - 1) acc += tn * A.g.n;
             if (i > 0) acc += tw * pr[i - 1];
             if (i < n - 1) acc += te * pr[i + 1];
-            if (r > 0) acc += ts * ps[((r + 2) % 3) * n + i];
-            if (r + 1 < n) acc += tn * ps[(F % 3) * n + i];
+            if (!C || r > 0) acc += ts * ps[((r + 2) % 3) * n + i];
+            if (!C || r + 1 < n) acc += tn * ps[(F % 3) * n + i];
             const double res = acc - (((tw + te) + ts) + tn) * x0;
             rr += res * res;
             A.r32[base + size_t(r) * n + i] = float(res);
@@ -80,6 +98,22 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
             }
             tn_prev = tn;
         }
+    };
+    const int lo = D;                          // first unchecked step (D >= 2)
+    const int hi = max(lo, ((n - D) / D) * D); // first checked step after them
+    int F0 = 0;
+    for (; F0 < lo; F0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) step(F0 + u, u, std::true_type{});
+    }
+    for (; F0 < hi; F0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) step(F0 + u, u, std::false_type{});
+    }
+    for (; F0 <= n; F0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u)
+            if (F0 + u <= n) step(F0 + u, u, std::true_type{});
     }
     for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
     __syncthreads();
