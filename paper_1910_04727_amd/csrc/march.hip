@@ -153,9 +153,9 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // straight-line steps in between, so the prefetches of the queue are never
     // conditional and no wait for outstanding loads is forced at a merge; the
     // step is a lambda there (that keeps these kernels within 128 registers).
-    // FP64: checked steps only, inline in the loop (its register rings leave
-    // no room for a second copy of the step, and behind a lambda the compiler
-    // kept one of its queues in scratch memory).
+    // FP64: the step inline in the loops (behind a lambda the compiler kept one
+    // of its queues in scratch memory); straight-line steps only in the
+    // pre-smoothing passes of the stage operator, checked steps elsewhere.
     if constexpr (sizeof(T) == 4) {
         auto step = [&](const int F, const int u, auto chk) {
             constexpr bool C = decltype(chk)::value;
@@ -177,6 +177,38 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (F0 + u <= LAST) step(F0 + u, u, std::true_type{});
+        }
+    } else if constexpr (CK && INIT != INIT_PROLONG) {
+        // FP64 stage-operator passes that start from x (pre-smoothing): their rings
+        // leave room for the straight-line steps (the other FP64 passes would spill)
+        const int lo = ((NH + 1 + U - 1) / U) * U;
+        const int hi = max(lo, ((n - U) / U) * U);
+        int F0 = 0;
+        for (; F0 < lo; F0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int F = F0 + u;
+                if (F > LAST) break;
+                constexpr bool C = true;
+#include "march_step.inc"
+            }
+        }
+        for (; F0 < hi; F0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int F = F0 + u;
+                constexpr bool C = false;
+#include "march_step.inc"
+            }
+        }
+        for (; F0 <= LAST; F0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int F = F0 + u;
+                if (F > LAST) break;
+                constexpr bool C = true;
+#include "march_step.inc"
+            }
         }
     } else {
         for (int F0 = 0; F0 <= LAST; F0 += U) {
