@@ -25,7 +25,7 @@ __device__ __forceinline__ T harm_s(T a, T b) {
 template <typename T>
 struct Lv {
     int n;
-    T *x, *b, *fx, *fy, *fxe, *fyn, *id;
+    T *x, *b, *fx, *fy, *fxe, *fyn;
 };
 
 // boundary values used by an interpolation (0 for a correction)
@@ -86,7 +86,7 @@ __device__ void half_sweep(const Lv<T> &L, int colour) {
     const int n = L.n, h = n >> 1;
     for (int c = threadIdx.x; c < n * h; c += blockDim.x) {
         const int j = c / h, i = 2 * (c % h) + ((j + colour) & 1);
-        L.x[j * n + i] = nbsum(L, i, j) * L.id[j * n + i];
+        L.x[j * n + i] = nbsum(L, i, j) * (T(1) / diag(L, i, j));
     }
     __syncthreads();
 }
@@ -99,7 +99,8 @@ __device__ void smooth(const Lv<T> &L, int nu) {
     }
 }
 
-// coarsest solve x = A^{-1} b in FP64: one lane per unknown
+// coarsest solve x = A^{-1} b in FP64: one lane per unknown (A^{-1} read from
+// global memory, where it stays in cache: it is 2 KB per sample)
 template <typename T>
 __device__ void coarse_solve(const double *Ainv, int N, const T *b, T *x) {
     if (threadIdx.x < N) {
@@ -118,10 +119,11 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     extern __shared__ unsigned char smem_raw[];
     T *const base = reinterpret_cast<T *>(smem_raw);
     const int top = A.top;
-    // level k arrays (x, b, fx, fy, id of n*n, then fxe and fyn of n), packed from level 0 up
+    // level k arrays (x, b, fx, fy of n*n, then fxe and fyn of n), packed from level 0 up;
+    // 1/diagonal is recomputed where needed, which keeps more samples resident per CU
     auto lv = [&](int k) -> Lv<T> {
         T *p = base;
-        for (int j = 0; j < k; ++j) p += 5 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
+        for (int j = 0; j < k; ++j) p += 4 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
         const int n = A.ns[k];
         Lv<T> L;
         L.n = n;
@@ -129,16 +131,15 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         L.b = p; p += n * n;
         L.fx = p; p += n * n;
         L.fy = p; p += n * n;
-        L.id = p; p += n * n;
         L.fxe = p; p += n;
         L.fyn = p;
         return L;
     };
     T *p = base;
-    for (int j = 0; j <= top; ++j) p += 5 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
-    double *Ls = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(p) + 7) & ~uintptr_t(7));
+    for (int j = 0; j <= top; ++j) p += 4 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
+    T *red = p;
     const int N0 = A.ns[0] * A.ns[0];
-    T *red = reinterpret_cast<T *>(Ls + N0 * N0);
+    const double *Ls = A.chol + size_t(s) * N0 * N0;
     const bool dns = A.g.all != 0;
     const G4<T> gsol{T(A.g.w), T(A.g.e), T(A.g.s), T(A.g.n), dns};
     const G4<T> gzero{T(0), T(0), T(0), T(0), dns};
@@ -168,14 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             }
         }
     }
-    for (int c = threadIdx.x; c < N0 * N0; c += blockDim.x) Ls[c] = A.chol[size_t(s) * N0 * N0 + c];
     __syncthreads();
-    for (int k = 0; k <= top; ++k) {
-        const Lv<T> Lk = lv(k);
-        const int n = Lk.n;
-        for (int c = threadIdx.x; c < n * n; c += blockDim.x)
-            Lk.id[c] = T(1) / diag(Lk, c % n, c / n);
-    }
     // right-hand side and initial guess on the top level
     {
         const Lv<T> Tp = lv(top);
@@ -297,11 +291,8 @@ int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out
     }
     if (S <= 0) return FMGMC_OK;
     size_t words = 0;
-    for (int k = 0; k <= a.top; ++k) words += 5 * size_t(a.ns[k]) * a.ns[k] + 2 * size_t(a.ns[k]);
-    const int N0 = a.ns[0] * a.ns[0];
-    size_t bytes = words * sizeof(T);
-    bytes = (bytes + 7) & ~size_t(7);
-    bytes += size_t(N0) * N0 * sizeof(double) + 8 * sizeof(T);
+    for (int k = 0; k <= a.top; ++k) words += 4 * size_t(a.ns[k]) * a.ns[k] + 2 * size_t(a.ns[k]);
+    const size_t bytes = (words + 8) * sizeof(T);  // the levels, then 8 reduction slots
     hipLaunchKernelGGL(k_small<T>, dim3(S), dim3(kThreads), bytes, st, a, init, rhs_array, out);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
