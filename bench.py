@@ -112,6 +112,18 @@ def roofline(form, steps):
             "alg_bytes_per_launch": alg / n}
 
 
+def pass_table(form):
+    """Per-kind figures of the three timed 512^2 stage passes: launches, mean
+    launch time and algorithmic GB/s (the roofline picks the largest total)."""
+    out = {}
+    for kind in ("pre", "post", "ir"):
+        ms, n, alg = form["prof"][kind]
+        if n:
+            out[kind] = {"launches": n, "avg_launch_us": round(1e3 * ms / n, 2),
+                         "achieved_gbs": round(alg / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def cpu_baseline(xi, n_samples):
     from oracle import oracle as O
     threads = O.max_threads()
@@ -667,6 +679,7 @@ def main():
             "status": f["rc"], "flagged_samples": f["flags"], "mean_Y": f["estimate"]["mean_y"],
             "warm_rejected": f["warm_rejected"],
             "roofline": roofline(f, args.steps),
+            "passes_512": pass_table(f),
             "kl_tflops": round(kl_flops / (kl_ms * 1e-3) / 1e12, 2) if kl_n else None,
             "kl_ms_per_step": round(kl_ms / args.steps, 3) if kl_n else None,
         }
