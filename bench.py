@@ -52,7 +52,7 @@ def run_form(torch, fmgmc, xi_dev, form, args):
     nu1, nu2 = (int(v) for v in args.nu.split(",")) if solver == "fp32_ir" else (2, 2)
     ctx = fmgmc.Context(**CFG, solver=solver, rel_tol=args.tol, max_batch=args.batch,
                         inner_cycles=args.inner, max_cycles=60, nu1=nu1, nu2=nu2, w_max_n=args.wmax,
-                        inner_first=args.inner_first)
+                        inner_first=args.inner_first, fuse_cycles=not args.no_fuse)
     net = None
     if form == "nn_warm":
         net = fmgmc.Cnn(path=WEIGHTS)
@@ -98,7 +98,7 @@ TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000}
 def roofline(form, steps):
     """Dominant HBM-bound kernel of a form from the library's event timing."""
     best = None
-    for kind in ("pre", "post", "ir"):
+    for kind in ("pre", "post", "ir", "fused"):
         ms, n, alg = form["prof"][kind]
         if n and (best is None or ms > best[1]):
             best = (kind, ms, n, alg)
@@ -116,7 +116,7 @@ def pass_table(form):
     """Per-kind figures of the three timed 512^2 stage passes: launches, mean
     launch time and algorithmic GB/s (the roofline picks the largest total)."""
     out = {}
-    for kind in ("pre", "post", "ir"):
+    for kind in ("pre", "post", "ir", "fused"):
         ms, n, alg = form["prof"][kind]
         if n:
             out[kind] = {"launches": n, "avg_launch_us": round(1e3 * ms / n, 2),
@@ -613,6 +613,8 @@ def main():
     ap.add_argument("--wmax", type=int, default=32, help="W-cycle coarse corrections on grids n <= wmax")
     ap.add_argument("--nu", default="2,2", help="pre,post smoothing sweeps of the FP32 cycles (1..4)")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="FP32 cycles back to back as separate post- and pre-smoothing passes")
     ap.add_argument("--forms", default="fp32_ir,fp64,nn_warm")
     ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
@@ -621,8 +623,8 @@ def main():
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the method's samples are independent; "
-              "multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py: measures one GPU only (the method's samples are independent, so the "
+              "path would shard by sample ranges; that sharding is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -666,7 +668,7 @@ def main():
                                f"sigma2=1, corr_len=0.2, 256 KL modes, {args.samples} samples, "
                                f"rel-res {args.tol:g}, form {head}",
                    "batch": args.batch, "inner_cycles": args.inner, "inner_first": args.inner_first,
-                   "w_max_n": args.wmax, "nu_fp32": args.nu},
+                   "w_max_n": args.wmax, "nu_fp32": args.nu, "fuse_cycles": not args.no_fuse},
         "roofline": roofline(H, args.steps),
     }
     out["forms"] = {}

@@ -112,6 +112,13 @@ typedef struct {
     int32_t separate_coarse; /* 0: Q^c_l from the FMG pass that yields Q^f_l (FMG-MLMC,
                                 Section 2.5); 1: Q^c_l from a separate FMG solve on n_l/2, as in
                                 standard MLMC (the comparator of the paper's saving) */
+    int32_t fuse_cycles;   /* FP32_IR: 1 = where FP32 V-cycles follow each other with no
+                              refinement between them, the post-smoothing pass of one cycle and
+                              the pre-smoothing pass of the next run as one pass over the stage
+                              grid (the same sweeps in the same order, with x, K and b read
+                              once instead of twice); needs nu1 + nu2 <= 4. 0 = separate
+                              passes. Converged results agree to the stopping tolerance; the
+                              FP32 iterates may differ in rounding. */
 } fmgmc_opts;
 
 typedef struct fmgmc_ctx fmgmc_ctx;
@@ -240,13 +247,15 @@ int fmgmc_kl_modes(double sigma2, double corr_len, int32_t n_modes, int32_t *a, 
  * 3 KL synthesis (flops of the path taken: 2 M n^2 per sample for the dense
  * contraction, 2 A n (A + n) for the separable one with A 1-D modes per
  * axis), 4 coarse-grid V-cycle in LDS, 5 warm-start network
- * inference (flops; all its layers, every QoI stage it runs on).
+ * inference (flops; all its layers, every QoI stage it runs on), 6 fused
+ * prolongation + post-smoothing + pre-smoothing + residual + restriction pass
+ * (fuse_cycles).
  * fmgmc_profile_read synchronises, returns the summed kernel time in ms,
  * the launch count and the algorithmic bytes (flops for kind 3), and clears
  * the kind's record.
  */
 enum { FMGMC_PROF_PRE = 0, FMGMC_PROF_POST = 1, FMGMC_PROF_IR = 2, FMGMC_PROF_KL = 3,
-       FMGMC_PROF_SMALL = 4, FMGMC_PROF_CNN = 5, FMGMC_PROF_KINDS = 6 };
+       FMGMC_PROF_SMALL = 4, FMGMC_PROF_CNN = 5, FMGMC_PROF_FUSED = 6, FMGMC_PROF_KINDS = 7 };
 int fmgmc_profile_enable(fmgmc_ctx *ctx, int32_t enable);
 int fmgmc_profile_read(fmgmc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *alg);
 

@@ -308,13 +308,20 @@ struct Bufs {
 Bufs<double> bufs64(Work &w) { return {w.K64, w.x64, w.b64, w.pf64}; }
 Bufs<float> bufs32(Work &w) { return {w.K32, w.x32, w.b32, w.pf32}; }
 
+// How a cycle's top-grid passes join its neighbours (FP32 cycles back to back):
+// VC_SKIP_PRE, the previous cycle's last pass already did this cycle's
+// pre-smoothing and restriction; VC_FUSE_POST, the post-smoothing pass also
+// does the next cycle's pre-smoothing and restriction.
+enum { VC_SKIP_PRE = 1, VC_FUSE_POST = 2 };
+
 // One cycle with top grid k: top operator from K (stage operator), the levels
 // below from correction pyramid q; V(nu1,nu2) on grids above w_max_n, two
 // coarse cycles (W) on grids n <= w_max_n. rhs_array: top rhs in b[k] (else the
 // Dirichlet data). init: INIT_ZERO / INIT_LOAD / INIT_INTERP (from x[k-1]).
+// flow (VC_*) only for a top grid above small_top, in FP32 with rhs_array.
 template <typename T>
 int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool rhs_array, int out_top,
-           hipStream_t st) {
+           hipStream_t st, int flow = 0) {
     const int nh1 = 2 * c->opts.nu1, nh2 = 2 * c->opts.nu2;
     const int N0 = W.nsz[0] * W.nsz[0];
     const Bnd g = bnd(c);
@@ -374,9 +381,18 @@ int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool
     const double b_pre = (init == INIT_ZERO ? 0.0 : (init == INIT_INTERP ? 0.25 * w : w)) + w /*K*/ +
                          (rhs_array ? w : 0.0) + w /*x out*/ + 0.25 * w /*restricted residual*/;
     const double b_post = w + 0.25 * w + w + (rhs_array ? w : 0.0) + w;
-    if (top) TRY(timed(c, W, FMGMC_PROF_PRE, act * cells * b_pre, st, [&] { return march(k, true, init, rhs_array, OUT_RESTRICT, nh1); }));
-    else TRY(march(k, true, init, rhs_array, OUT_RESTRICT, nh1));
+    if (!(flow & VC_SKIP_PRE)) {
+        if (top) TRY(timed(c, W, FMGMC_PROF_PRE, act * cells * b_pre, st, [&] { return march(k, true, init, rhs_array, OUT_RESTRICT, nh1); }));
+        else TRY(march(k, true, init, rhs_array, OUT_RESTRICT, nh1));
+    }
     for (int g = 0; g < gamma(k - 1); ++g) TRY(corr(k - 1, g == 0 ? INIT_ZERO : INIT_LOAD));
+    if (flow & VC_FUSE_POST) {
+        // x, coarse correction, K, b in; x and the restricted residual out
+        const double b_fused = w + 0.25 * w + w + w + w + 0.25 * w;
+        if (top) TRY(timed(c, W, FMGMC_PROF_FUSED, act * cells * b_fused, st, [&] { return march(k, true, INIT_PROLONG, true, OUT_RESTRICT, nh2 + nh1); }));
+        else TRY(march(k, true, INIT_PROLONG, true, OUT_RESTRICT, nh2 + nh1));
+        return FMGMC_OK;
+    }
     if (top) TRY(timed(c, W, FMGMC_PROF_POST, act * cells * b_post, st, [&] { return march(k, true, INIT_PROLONG, rhs_array, out_top, nh2); }));
     else TRY(march(k, true, INIT_PROLONG, rhs_array, out_top, nh2));
     return FMGMC_OK;
@@ -630,9 +646,13 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             // FP32 cycles before the first FP64 refinement, and per refinement after it
             const int inner = std::max(1, c->opts.inner_cycles);
             const int first = std::min(c->opts.inner_first > 0 ? c->opts.inner_first : inner, c->opts.max_cycles);
+            // back-to-back cycles on a marching top grid share their joining pass
+            const bool fuse = c->opts.fuse_cycles && k > c->small_top && c->opts.nu1 + c->opts.nu2 <= 4;
             auto step = [&](int ni) -> int {
-                for (int ic = 0; ic < ni; ++ic)
-                    TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st));
+                for (int ic = 0; ic < ni; ++ic) {
+                    const int flow = fuse ? ((ic > 0 ? VC_SKIP_PRE : 0) | (ic + 1 < ni ? VC_FUSE_POST : 0)) : 0;
+                    TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st, flow));
+                }
                 IRArgs iu = ia;
                 iu.e = W.x32[k];
                 const double irb = double(W.n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
@@ -672,6 +692,7 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
         return FMGMC_EINVAL;
     if (o->solver == FMGMC_SOLVER_FP32_IR && h->n0 < 8) return FMGMC_EINVAL;  // QoI stages need n >= 8
     if (o->max_batch < 0 || o->w_max_n < 0 || o->separate_coarse < 0 || o->separate_coarse > 1) return FMGMC_EINVAL;
+    if (o->fuse_cycles < 0 || o->fuse_cycles > 1) return FMGMC_EINVAL;
     return FMGMC_OK;
 }
 

@@ -259,6 +259,11 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
     FMGMC_MARCH_CASE(true, INIT_ZERO, true, OUT_RESTRICT)
     FMGMC_MARCH_CASE(true, INIT_LOAD, true, OUT_RESTRICT)
     FMGMC_MARCH_CASE(true, INIT_PROLONG, true, 0)
+    if constexpr (sizeof(T) == 4) {
+        // FP32 cycles back to back: prolongation and post-smoothing of one
+        // cycle, then pre-smoothing and restriction of the next, in one pass
+        FMGMC_MARCH_CASE(true, INIT_PROLONG, true, OUT_RESTRICT)
+    }
     // correction operators (levels below the top)
     FMGMC_MARCH_CASE(false, INIT_ZERO, true, OUT_RESTRICT)
     FMGMC_MARCH_CASE(false, INIT_LOAD, true, OUT_RESTRICT)

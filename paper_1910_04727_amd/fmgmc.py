@@ -41,7 +41,7 @@ class Opts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("kl_prec", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("inner_cycles", C.c_int32),
                 ("max_batch", C.c_int32), ("w_max_n", C.c_int32), ("rel_tol", C.c_double),
-                ("inner_first", C.c_int32), ("separate_coarse", C.c_int32)]
+                ("inner_first", C.c_int32), ("separate_coarse", C.c_int32), ("fuse_cycles", C.c_int32)]
 
 
 class LevelEst(C.Structure):
@@ -150,7 +150,7 @@ class Context:
     def __init__(self, sigma2, corr_len, n_modes, n_levels, n0, solver="fp64", kl_prec="fp64",
                  nu1=2, nu2=2, max_cycles=50, inner_cycles=1, max_batch=0, rel_tol=1e-10,
                  p_west=None, p_east=None, device=0, w_max_n=64, inner_first=0, separate_coarse=False,
-                 case=2, p_south=None, p_north=None):
+                 case=2, p_south=None, p_north=None, fuse_cycles=True):
         if case not in BOUNDARY_DEFAULTS:
             raise ValueError("case must be 1 or 2 (Table 1)")
         g = [d if v is None else float(v) for d, v in zip(BOUNDARY_DEFAULTS[case], (p_west, p_east, p_south, p_north))]
@@ -158,7 +158,8 @@ class Context:
         self.field = Field(sigma2, corr_len, n_modes, 0)
         self.hier = Hier(n_levels, n0, 4, 1 if case == 1 else 0, *g)
         self.opts = Opts(SOLVERS[solver], KL_PREC[kl_prec], nu1, nu2, max_cycles, inner_cycles,
-                         max_batch, w_max_n, rel_tol, inner_first, 1 if separate_coarse else 0)
+                         max_batch, w_max_n, rel_tol, inner_first, 1 if separate_coarse else 0,
+                         1 if fuse_cycles else 0)
         self.n_modes = n_modes
         self.n0 = n0
         self.n_levels = n_levels
@@ -184,7 +185,7 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    PROF_KINDS = ("pre", "post", "ir", "kl", "small", "cnn")
+    PROF_KINDS = ("pre", "post", "ir", "kl", "small", "cnn", "fused")
 
     def profile(self, enable=True):
         _check(lib().fmgmc_profile_enable(self._h, 1 if enable else 0))
