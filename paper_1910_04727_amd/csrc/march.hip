@@ -147,6 +147,16 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     V2<T> bprev{T(0), T(0)}, bcur{T(0), T(0)};
     T eprev = T(0), ecur = T(0);                 // east boundary face of rows F-1, F (correction)
     T rprev = T(0), rr = T(0), q = T(0);
+    // FP32: this lane's cell pairs of the rows in flight (hv[t], the row that
+    // half-sweep t acted on last; hv[0], the row that entered last; hres, the
+    // row below the residual's row), so that the sweeps read only the west /
+    // east neighbours from LDS. FP64 reads them from the LDS ring (its
+    // register rings leave no room).
+    constexpr bool RC = sizeof(T) == 4;
+    V2<T> hv[NH + 1];
+#pragma unroll
+    for (int t = 0; t <= NH; ++t) hv[t] = V2<T>{T(0), T(0)};
+    V2<T> hres{T(0), T(0)};
 
     const int LAST = n - 1 + NH + (RES ? 1 : 0);
     // Row steps (march_step.inc). FP32: range-checked steps at both ends and
