@@ -92,7 +92,7 @@ def run_form(torch, fmgmc, xi_dev, form, args):
 # Measured HBM traffic / algorithmic bytes of the dominant kernels, from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
 # (profiles/hbm_traffic_512.md). None once a kernel changes after measurement.
-TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000}
+TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000, "fused": 1.000}
 
 
 def roofline(form, steps):
