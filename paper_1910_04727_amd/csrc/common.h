@@ -20,6 +20,17 @@ void set_error(const std::string &msg);
         }                                                                                      \
     } while (0)
 
+// 1/x on the device: the hardware reciprocal (FP32, within 1 ulp); in FP64
+// refined by two Newton steps to full double precision
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 // ---------------------------------------------------------------- KL table
 struct ModeTable {
     int M = 0;

@@ -31,16 +31,6 @@ struct V2 {
     T a, b;
 };
 
-__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_(double x) {
-    // hardware reciprocal refined by two Newton steps (full double precision)
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
-}
-
 template <typename T>
 __device__ __forceinline__ T harm(T a, T b) {
     return T(2) * a * b * rcp_(a + b);

@@ -24,7 +24,7 @@ __device__ __forceinline__ T harm_s(T a, T b) {
 
 template <typename T>
 struct Lv {
-    int n;
+    int n, lg;  // n = 2^lg cells per side
     T *x, *b, *fx, *fy, *fxe, *fyn;
 };
 
@@ -61,15 +61,43 @@ __device__ __forceinline__ T interp_at(const T *c, int nc, int i, int j, const G
            T(16);
 }
 
-// sum over interior neighbours of T_nb x_nb, plus b
+// bilinear prolongation of a correction (homogeneous boundary data): the
+// ghost value beyond a Dirichlet side is minus the edge value, beyond a
+// no-flow side the edge value itself (interp_at with zero data, without its
+// branches)
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T *c, int nc, int lgc, int i, int j, bool all) {
+    const int I = i >> 1, J = j >> 1;
+    const int I1 = I + ((i & 1) ? 1 : -1), J1 = J + ((j & 1) ? 1 : -1);
+    const bool ox = I1 < 0 || I1 >= nc, oy = J1 < 0 || J1 >= nc;
+    const int Ic = ox ? I : I1, Jc = oy ? J : J1;
+    const T a = c[(J << lgc) + I];
+    T bx = c[(J << lgc) + Ic], by = c[(Jc << lgc) + I], bxy = c[(Jc << lgc) + Ic];
+    if (ox) {
+        bx = -bx;
+        bxy = -bxy;
+    }
+    if (oy && all) {
+        by = -by;
+        bxy = -bxy;
+    }
+    return (T(9) * a + T(3) * bx + T(3) * by + bxy) / T(16);
+}
+
+// sum over interior neighbours of T_nb x_nb, plus b (a side without an
+// interior neighbour adds 0 * x of the cell itself, so every lane runs the
+// same instructions and the sum keeps its order)
 template <typename T>
 __device__ __forceinline__ T nbsum(const Lv<T> &L, int i, int j) {
     const int n = L.n, P = j * n + i;
+    const bool w = i > 0, e = i < n - 1, so = j > 0, no = j < n - 1;
+    const T tw = w ? L.fx[P] : T(0), te = e ? L.fx[P + 1] : T(0);
+    const T ts = so ? L.fy[P] : T(0), tn = no ? L.fy[P + n] : T(0);
     T acc = L.b[P];
-    if (i > 0) acc += L.fx[P] * L.x[P - 1];
-    if (i < n - 1) acc += L.fx[P + 1] * L.x[P + 1];
-    if (j > 0) acc += L.fy[P] * L.x[P - n];
-    if (j < n - 1) acc += L.fy[P + n] * L.x[P + n];
+    acc += tw * L.x[w ? P - 1 : P];
+    acc += te * L.x[e ? P + 1 : P];
+    acc += ts * L.x[so ? P - n : P];
+    acc += tn * L.x[no ? P + n : P];
     return acc;
 }
 
@@ -85,7 +113,7 @@ template <typename T>
 __device__ void half_sweep(const Lv<T> &L, int colour) {
     const int n = L.n, h = n >> 1;
     for (int c = threadIdx.x; c < n * h; c += blockDim.x) {
-        const int j = c / h, i = 2 * (c % h) + ((j + colour) & 1);
+        const int j = c >> (L.lg - 1), i = 2 * (c & (h - 1)) + ((j + colour) & 1);
         L.x[j * n + i] = nbsum(L, i, j) * (T(1) / diag(L, i, j));
     }
     __syncthreads();
@@ -99,14 +127,24 @@ __device__ void smooth(const Lv<T> &L, int nu) {
     }
 }
 
-// coarsest solve x = A^{-1} b in FP64: one lane per unknown (A^{-1} read from
-// global memory, where it stays in cache: it is 2 KB per sample)
+// coarsest solve x = A^{-1} b in FP64 on the 4 x 4 grid: one lane per
+// unknown (A^{-1} read from global memory, where it stays in cache: it is
+// 2 KB per sample). The row is loaded whole before the products, so its loads
+// overlap; the sum runs in k order.
+constexpr int kN0 = 16;  // unknowns of the coarsest grid
 template <typename T>
-__device__ void coarse_solve(const double *Ainv, int N, const T *b, T *x) {
-    if (threadIdx.x < N) {
-        const double *row = Ainv + threadIdx.x * N;
+__device__ void coarse_solve(const double *Ainv, const T *b, T *x) {
+    if (threadIdx.x < kN0) {
+        const double *row = Ainv + threadIdx.x * kN0;
+        double a[kN0];
+        T bv[kN0];
+#pragma unroll
+        for (int k = 0; k < kN0; ++k) a[k] = row[k];
+#pragma unroll
+        for (int k = 0; k < kN0; ++k) bv[k] = b[k];
         double s = 0.0;
-        for (int k = 0; k < N; ++k) s += row[k] * double(b[k]);
+#pragma unroll
+        for (int k = 0; k < kN0; ++k) s += a[k] * double(bv[k]);
         x[threadIdx.x] = T(s);
     }
     __syncthreads();
@@ -127,6 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         const int n = A.ns[k];
         Lv<T> L;
         L.n = n;
+        L.lg = __builtin_ctz(n);
         L.x = p; p += n * n;
         L.b = p; p += n * n;
         L.fx = p; p += n * n;
@@ -149,16 +188,20 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         const int n = Lk.n, nn = n * n;
         if (k == top && A.top_from_k) {
             const T *K = A.Ktop + size_t(s) * nn;
+#pragma unroll 4
             for (int c = threadIdx.x; c < nn; c += blockDim.x) {
-                const int i = c % n, j = c / n;
-                Lk.fx[c] = i == 0 ? T(2) * K[c] : harm_s(K[c - 1], K[c]);
-                Lk.fy[c] = j == 0 ? (dns ? T(2) * K[c] : T(0)) : harm_s(K[c - n], K[c]);
-                if (i == n - 1) Lk.fxe[j] = T(2) * K[c];
-                if (j == n - 1) Lk.fyn[i] = dns ? T(2) * K[c] : T(0);
+                const int i = c & (n - 1), j = c >> Lk.lg;
+                // the west and south neighbours' K, loaded without a branch (own K at an edge)
+                const T kc = K[c], kw = K[i > 0 ? c - 1 : c], ksn = K[j > 0 ? c - n : c];
+                Lk.fx[c] = i == 0 ? T(2) * kc : harm_s(kw, kc);
+                Lk.fy[c] = j == 0 ? (dns ? T(2) * kc : T(0)) : harm_s(ksn, kc);
+                if (i == n - 1) Lk.fxe[j] = T(2) * kc;
+                if (j == n - 1) Lk.fyn[i] = dns ? T(2) * kc : T(0);
             }
         } else {
             const T *fx = A.f[k].fx + size_t(s) * nn, *fy = A.f[k].fy + size_t(s) * nn;
             const T *fe = A.f[k].fxe + size_t(s) * n, *fn = A.f[k].fyn + size_t(s) * n;
+#pragma unroll 4
             for (int c = threadIdx.x; c < nn; c += blockDim.x) {
                 Lk.fx[c] = fx[c];
                 Lk.fy[c] = fy[c];
@@ -174,8 +217,9 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     {
         const Lv<T> Tp = lv(top);
         const int n = Tp.n, nn = n * n;
+#pragma unroll 4
         for (int c = threadIdx.x; c < nn; c += blockDim.x) {
-            const int i = c % n, j = c / n;
+            const int i = c & (n - 1), j = c >> Tp.lg;
             if (rhs_array) {
                 Tp.b[c] = A.b[size_t(s) * nn + c];
             } else {
@@ -205,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         if (down) {
             if (k == 0) {
                 const Lv<T> L0 = lv(0);
-                coarse_solve(Ls, N0, L0.b, L0.x);
+                coarse_solve(Ls, L0.b, L0.x);
                 if (top == 0) break;
                 k = 1;
                 down = false;
@@ -215,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             smooth(Lk, A.nu1);
             const int n = Lk.n, nc = n / 2;
             for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
-                const int I = c % nc, J = c / nc;
+                const int I = c & (nc - 1), J = c >> (Lk.lg - 1);
                 T acc = T(0);
                 for (int dj = 0; dj < 2; ++dj)
                     for (int di = 0; di < 2; ++di) {
@@ -240,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
             const int n = Lk.n, nc = n / 2;
             for (int c = threadIdx.x; c < n * n; c += blockDim.x)
-                Lk.x[c] += interp_at(Lc.x, nc, c % n, c / n, gzero);
+                Lk.x[c] += prolong_at(Lc.x, nc, Lc.lg, c & (n - 1), c >> Lk.lg, dns);
             __syncthreads();
             smooth(Lk, A.nu2);
             if (k == top) break;
@@ -255,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     if (out & OUT_RR) {
         T rr = T(0);
         for (int c = threadIdx.x; c < nn; c += blockDim.x) {
-            const int i = c % n, j = c / n;
+            const int i = c & (n - 1), j = c >> Tp.lg;
             const T r = nbsum(Tp, i, j) - diag(Tp, i, j) * Tp.x[c];
             rr += r * r;
         }
@@ -285,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
 
 template <typename T>
 int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out, hipStream_t st) {
-    if (a.top < 0 || a.top >= kMaxLev || a.ns[0] * a.ns[0] > 16) {
+    if (a.top < 0 || a.top >= kMaxLev || a.ns[0] * a.ns[0] != kN0) {
         set_error("launch_small: unsupported hierarchy");
         return FMGMC_EINVAL;
     }
