@@ -112,7 +112,7 @@ __device__ __forceinline__ T diag(const Lv<T> &L, int i, int j) {
 template <typename T>
 __device__ void half_sweep(const Lv<T> &L, int colour) {
     const int n = L.n, h = n >> 1;
-    for (int c = threadIdx.x; c < n * h; c += blockDim.x) {
+    for (int c = threadIdx.x; c < n * h; c += kThreads) {
         const int j = c >> (L.lg - 1), i = 2 * (c & (h - 1)) + ((j + colour) & 1);
         L.x[j * n + i] = nbsum(L, i, j) * (T(1) / diag(L, i, j));
     }
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         if (k == top && A.top_from_k) {
             const T *K = A.Ktop + size_t(s) * nn;
 #pragma unroll 4
-            for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+            for (int c = threadIdx.x; c < nn; c += kThreads) {
                 const int i = c & (n - 1), j = c >> Lk.lg;
                 // the west and south neighbours' K, loaded without a branch (own K at an edge)
                 const T kc = K[c], kw = K[i > 0 ? c - 1 : c], ksn = K[j > 0 ? c - n : c];
@@ -202,11 +202,11 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             const T *fx = A.f[k].fx + size_t(s) * nn, *fy = A.f[k].fy + size_t(s) * nn;
             const T *fe = A.f[k].fxe + size_t(s) * n, *fn = A.f[k].fyn + size_t(s) * n;
 #pragma unroll 4
-            for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+            for (int c = threadIdx.x; c < nn; c += kThreads) {
                 Lk.fx[c] = fx[c];
                 Lk.fy[c] = fy[c];
             }
-            for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            for (int c = threadIdx.x; c < n; c += kThreads) {
                 Lk.fxe[c] = fe[c];
                 Lk.fyn[c] = fn[c];
             }
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         const Lv<T> Tp = lv(top);
         const int n = Tp.n, nn = n * n;
 #pragma unroll 4
-        for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+        for (int c = threadIdx.x; c < nn; c += kThreads) {
             const int i = c & (n - 1), j = c >> Tp.lg;
             if (rhs_array) {
                 Tp.b[c] = A.b[size_t(s) * nn + c];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
             smooth(Lk, A.nu1);
             const int n = Lk.n, nc = n / 2;
-            for (int c = threadIdx.x; c < nc * nc; c += blockDim.x) {
+            for (int c = threadIdx.x; c < nc * nc; c += kThreads) {
                 const int I = c & (nc - 1), J = c >> (Lk.lg - 1);
                 T acc = T(0);
                 for (int dj = 0; dj < 2; ++dj)
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             }
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
             const int n = Lk.n, nc = n / 2;
-            for (int c = threadIdx.x; c < n * n; c += blockDim.x)
+            for (int c = threadIdx.x; c < n * n; c += kThreads)
                 Lk.x[c] += prolong_at(Lc.x, nc, Lc.lg, c & (n - 1), c >> Lk.lg, dns);
             __syncthreads();
             smooth(Lk, A.nu2);
@@ -295,10 +295,10 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     // outputs
     const Lv<T> Tp = lv(top);
     const int n = Tp.n, nn = n * n;
-    for (int c = threadIdx.x; c < nn; c += blockDim.x) A.x[size_t(s) * nn + c] = Tp.x[c];
+    for (int c = threadIdx.x; c < nn; c += kThreads) A.x[size_t(s) * nn + c] = Tp.x[c];
     if (out & OUT_RR) {
         T rr = T(0);
-        for (int c = threadIdx.x; c < nn; c += blockDim.x) {
+        for (int c = threadIdx.x; c < nn; c += kThreads) {
             const int i = c & (n - 1), j = c >> Tp.lg;
             const T r = nbsum(Tp, i, j) - diag(Tp, i, j) * Tp.x[c];
             rr += r * r;
