@@ -301,25 +301,27 @@ template int launch_march<float>(const MarchArgs<float> &, int, int, bool, int, 
 // north boundary faces 2K (north: 0 in Case II).
 template <typename T>
 __global__ void k_faces_from_k(int n, const T *__restrict__ K, Faces<T> out, int nc, int all) {
-    // coarse cell (I, J) of the n/2 grid from the four faces of the fine operator on it
+    // coarse cell (I, J) of the n/2 grid from the four faces of the fine operator on it:
+    // K of fine rows 2J-1, 2J, 2J+1 at columns 2I-1, 2I, 2I+1 (cell pairs as one load)
     const int s = blockIdx.y;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc * nc) return;
-    const int I = c % nc, J = c / nc;
+    const int I = c & (nc - 1), J = c >> (31 - __builtin_clz(nc));
+    const int i0 = 2 * I, j0 = 2 * J;
     const T *k = K + size_t(s) * n * n;
-    auto kk = [&](int i, int j) { return k[size_t(j) * n + i]; };
-    auto fxf = [&](int i, int j) -> T { return i == 0 ? T(2) * kk(0, j) : harm(kk(i - 1, j), kk(i, j)); };
-    auto fyf = [&](int i, int j) -> T {
-        return j == 0 ? (all ? T(2) * kk(i, 0) : T(0)) : harm(kk(i, j - 1), kk(i, j));
-    };
+    const V2<T> r0 = ld2(k + size_t(j0) * n + i0);        // K(i0, j0), K(i0+1, j0)
+    const V2<T> r1 = ld2(k + size_t(j0 + 1) * n + i0);    // K(i0, j0+1), K(i0+1, j0+1)
+    const V2<T> rs = J > 0 ? ld2(k + size_t(j0 - 1) * n + i0) : r0;  // row j0-1
+    const T w0 = I > 0 ? k[size_t(j0) * n + i0 - 1] : r0.a, w1 = I > 0 ? k[size_t(j0 + 1) * n + i0 - 1] : r1.a;
+    const T fx0 = I == 0 ? T(2) * r0.a : harm(w0, r0.a);
+    const T fx1 = I == 0 ? T(2) * r1.a : harm(w1, r1.a);
+    const T fy0 = J == 0 ? (all ? T(2) * r0.a : T(0)) : harm(rs.a, r0.a);
+    const T fy1 = J == 0 ? (all ? T(2) * r0.b : T(0)) : harm(rs.b, r0.b);
     const size_t o = size_t(s) * nc * nc + size_t(J) * nc + I;
-    out.fx[o] = T(0.5) * (fxf(2 * I, 2 * J) + fxf(2 * I, 2 * J + 1));
-    out.fy[o] = T(0.5) * (fyf(2 * I, 2 * J) + fyf(2 * I + 1, 2 * J));
-    if (I == nc - 1)
-        out.fxe[size_t(s) * nc + J] = T(0.5) * (T(2) * kk(n - 1, 2 * J) + T(2) * kk(n - 1, 2 * J + 1));
-    if (J == nc - 1)
-        out.fyn[size_t(s) * nc + I] =
-            all ? T(0.5) * (T(2) * kk(2 * I, n - 1) + T(2) * kk(2 * I + 1, n - 1)) : T(0);
+    out.fx[o] = T(0.5) * (fx0 + fx1);
+    out.fy[o] = T(0.5) * (fy0 + fy1);
+    if (I == nc - 1) out.fxe[size_t(s) * nc + J] = T(0.5) * (T(2) * r0.b + T(2) * r1.b);
+    if (J == nc - 1) out.fyn[size_t(s) * nc + I] = all ? T(0.5) * (T(2) * r1.a + T(2) * r1.b) : T(0);
 }
 
 template <typename T>

@@ -12,23 +12,6 @@ namespace {
 
 __device__ __forceinline__ double harm_d(double a, double b) { return 2.0 * a * b / (a + b); }
 
-// coarse value at (I, J) with ghosts: beyond the south / north side a mirror
-// (no flow) or 2 g - value (Dirichlet), then beyond the west / east side
-// 2 g - the edge value of that (possibly ghost) row
-template <typename T>
-__device__ __forceinline__ double ghost_row_d(const T *c, int nc, int I, int J, const Bnd &g) {
-    if (J >= 0 && J < nc) return double(c[J * nc + I]);
-    const int Jc = J < 0 ? 0 : nc - 1;
-    return g.all ? 2.0 * (J < 0 ? g.s : g.n) - double(c[Jc * nc + I]) : double(c[Jc * nc + I]);
-}
-
-template <typename T>
-__device__ __forceinline__ double ghost_d(const T *c, int nc, int I, int J, const Bnd &g) {
-    if (I < 0) return 2.0 * g.w - ghost_row_d(c, nc, 0, J, g);
-    if (I >= nc) return 2.0 * g.e - ghost_row_d(c, nc, nc - 1, J, g);
-    return ghost_row_d(c, nc, I, J, g);
-}
-
 // Refinement pass, marching over rows (one workgroup per sample, one lane per
 // column): p <- p + e; r = b - A p in FP64 with the stage operator; r is
 // handed to the next FP32 cycles, ||r||^2 and the QoI accumulate (east
@@ -145,13 +128,32 @@ __global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active
     const int nc = n / 2;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc * nc) return;
-    const int I = c % nc, J = c / nc;
+    const int lgc = 31 - __builtin_clz(nc);
+    const int I = c & (nc - 1), J = c >> lgc;
     const TS *x = xc + size_t(s) * nc * nc;
+    // the 3 x 3 coarse neighbourhood with ghosts: beyond the south / north
+    // side a mirror (no flow) or 2 g - value (Dirichlet), then beyond the
+    // west / east side 2 g - the edge value of that (possibly ghost) row;
+    // taken from the clamped neighbour by selects, so every lane runs the
+    // same instructions
     double v[3][3];
 #pragma unroll
-    for (int dj = -1; dj <= 1; ++dj)
+    for (int dj = -1; dj <= 1; ++dj) {
+        const int Jn = J + dj;
+        const bool oy = Jn < 0 || Jn >= nc;
+        const int Jc = oy ? J : Jn;
+        const bool fy = oy && g.all;
+        const double ay = fy ? 2.0 * (Jn < 0 ? g.s : g.n) : 0.0;
 #pragma unroll
-        for (int di = -1; di <= 1; ++di) v[dj + 1][di + 1] = ghost_d(x, nc, I + di, J + dj, g);
+        for (int di = -1; di <= 1; ++di) {
+            const int In = I + di;
+            const bool ox = In < 0 || In >= nc;
+            const int Ic = ox ? I : In;
+            const double cv = double(x[(Jc << lgc) + Ic]);
+            const double row = fy ? ay - cv : cv;
+            v[dj + 1][di + 1] = ox ? 2.0 * (In < 0 ? g.w : g.e) - row : row;
+        }
+    }
     double *o = p + size_t(s) * n * n + size_t(2 * J) * n + 2 * I;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
