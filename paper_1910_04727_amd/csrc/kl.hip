@@ -286,8 +286,9 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
                 const int j = j0 + 16 * g + 4 * v + r0;
                 const double kv = exp(acc[g][v]);
                 const size_t o = size_t(s) * n * n + size_t(j) * n + i;
-                if (A.K64[0]) A.K64[0][o] = kv;
-                if (A.K32[0]) A.K32[0][o] = float(kv);
+                // the fine field streams out (read back only by later passes)
+                if (A.K64[0]) __builtin_nontemporal_store(kv, A.K64[0] + o);
+                if (A.K32[0]) __builtin_nontemporal_store(float(kv), A.K32[0] + o);
                 if (even) store_coarse(A, s, i, j, kv);
             }
         }

@@ -56,6 +56,21 @@ __device__ __forceinline__ void st2(T *p, T a, T b) {
     }
 }
 
+// streamed operands (each read or written once per pass, so caching them only
+// displaces data that is reused): non-temporal 2-cell loads and stores
+template <typename T>
+__device__ __forceinline__ V2<T> ld2_nt(const T *p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    return {v.x, v.y};
+}
+
+template <typename T>
+__device__ __forceinline__ void st2_nt(T *p, T a, T b) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(v2{a, b}, reinterpret_cast<v2 *>(p));
+}
+
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T *red) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -109,15 +124,15 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     T qc[U], qe[U];
     auto fetch = [&](int slot, int row) {
         const size_t idx = base + size_t(row) * n + 2 * l;
-        if (LX) qx[slot] = ld2(A.x + idx);
+        if (LX) qx[slot] = ld2_nt(A.x + idx);
         if (CK) {
-            qk[slot] = ld2(A.K + idx);
+            qk[slot] = ld2_nt(A.K + idx);
         } else {
-            qk[slot] = ld2(A.f.fx + idx);
-            qf[slot] = ld2(A.f.fy + idx);
+            qk[slot] = ld2_nt(A.f.fx + idx);
+            qf[slot] = ld2_nt(A.f.fy + idx);
             qe[slot] = A.f.fxe[size_t(s) * n + row];
         }
-        if (RHSA) qb[slot] = ld2(A.b + idx);
+        if (RHSA) qb[slot] = ld2_nt(A.b + idx);
         if (CO) {
             const int J = min((row + 1) >> 1, nc - 1);
             qc[slot] = A.xc[cbase + size_t(J) * nc + l];

@@ -33,9 +33,9 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
     float qe[D];
     auto fetch = [&](int slot, int row) {
         const size_t idx = base + size_t(row) * n + i;
-        qp[slot] = A.p[idx];
-        if (A.e) qe[slot] = A.e[idx];
-        qk[slot] = A.K[idx];
+        qp[slot] = __builtin_nontemporal_load(A.p + idx);
+        if (A.e) qe[slot] = __builtin_nontemporal_load(A.e + idx);
+        qk[slot] = __builtin_nontemporal_load(A.K + idx);
     };
 #pragma unroll
     for (int d = 0; d < D; ++d)
@@ -72,8 +72,9 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
             if (!C || r + 1 < n) acc += tn * ps[(F % 3) * n + i];
             const double res = acc - (((tw + te) + ts) + tn) * x0;
             rr += res * res;
-            A.r32[base + size_t(r) * n + i] = float(res);
-            if (A.e) A.p[base + size_t(r) * n + i] = x0;
+            // streamed results (read back only by a later pass): non-temporal stores
+            __builtin_nontemporal_store(float(res), A.r32 + base + size_t(r) * n + i);
+            if (A.e) __builtin_nontemporal_store(x0, A.p + base + size_t(r) * n + i);
             if (!dns) {
                 if (i == n - 1) q += te * (x0 - A.g.e);
             } else if ((r == (n >> 1) - 1 || r == (n >> 1)) && (i == (n >> 1) - 1 || i == (n >> 1))) {
@@ -164,7 +165,8 @@ __global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active
             const int di = a ? 1 : -1;
             out[a] = (9.0 * v[1][1] + 3.0 * v[1][1 + di] + 3.0 * v[1 + dj][1] + v[1 + dj][1 + di]) / 16.0;
         }
-        *reinterpret_cast<double2 *>(o + size_t(b) * n) = make_double2(out[0], out[1]);
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(d2v{out[0], out[1]}, reinterpret_cast<d2v *>(o + size_t(b) * n));
     }
 }
 
