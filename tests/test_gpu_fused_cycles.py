@@ -125,3 +125,19 @@ def test_fused_512_at_1e10_agrees_with_separate():
     pick = [0, 127]
     oqf, _, _, _ = oracle(cfg, 512, level, xi[pick], tol=1e-10, max_cycles=60, wmax=32, nthreads=2)
     assert np.max(np.abs(qf1[pick] - oqf) / np.abs(oqf)) <= 1e-6
+
+
+def test_fused_at_the_largest_grid():
+    """1024^2 top grid (the fused pass then holds 16 ring rows of 1028 cells in LDS), rough
+    field of the six-level configuration (sigma2 = 3, corr_len 0.05, 1024 modes)."""
+    cfg = dict(sigma2=3.0, corr_len=0.05, n_modes=1024, n_levels=6, n0=32)
+    level, S = 5, 4
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=4, level=level)
+    log(f"fused FP32 cycles at 1024^2, sigma2 3, S {S}, tol 1e-12")
+    with fmgmc.Context(**cfg, solver="fp32_ir", rel_tol=1e-12, max_cycles=80, w_max_n=32, inner_first=4) as ctx:
+        rc, qf, qc, cyc, fl, prof = run(ctx, level, xi)
+    assert rc == fmgmc.OK and np.all(fl == 0) and prof["fused"][1] == 3
+    oqf, oqc, _, _ = oracle(cfg, 1024, level, xi, tol=1e-12, max_cycles=80, wmax=32, nthreads=4)
+    e = max(np.max(np.abs(qf - oqf) / np.abs(oqf)), np.max(np.abs(qc - oqc) / np.abs(oqc)))
+    log(f"  vs oracle {e:.2e}; cycles {cyc.tolist()}")
+    assert e <= 1e-8
