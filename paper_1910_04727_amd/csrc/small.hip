@@ -110,20 +110,20 @@ __device__ __forceinline__ T diag(const Lv<T> &L, int i, int j) {
 }
 
 template <typename T>
-__device__ void half_sweep(const Lv<T> &L, int colour) {
+__device__ void half_sweep(const Lv<T> &L, int colour, int tid) {
     const int n = L.n, h = n >> 1;
-    for (int c = threadIdx.x; c < n * h; c += kThreads) {
+    for (int c = tid; c < n * h; c += kThreads) {
         const int j = c >> (L.lg - 1), i = 2 * (c & (h - 1)) + ((j + colour) & 1);
-        L.x[j * n + i] = nbsum(L, i, j) * (T(1) / diag(L, i, j));
+        L.x[j * n + i] = nbsum(L, i, j) * rcp_(diag(L, i, j));
     }
     __syncthreads();
 }
 
 template <typename T>
-__device__ void smooth(const Lv<T> &L, int nu) {
+__device__ void smooth(const Lv<T> &L, int nu, int tid) {
     for (int k = 0; k < nu; ++k) {
-        half_sweep(L, 0);
-        half_sweep(L, 1);
+        half_sweep(L, 0, tid);
+        half_sweep(L, 1, tid);
     }
 }
 
@@ -133,9 +133,9 @@ __device__ void smooth(const Lv<T> &L, int nu) {
 // overlap; the sum runs in k order.
 constexpr int kN0 = 16;  // unknowns of the coarsest grid
 template <typename T>
-__device__ void coarse_solve(const double *Ainv, const T *b, T *x) {
-    if (threadIdx.x < kN0) {
-        const double *row = Ainv + threadIdx.x * kN0;
+__device__ void coarse_solve(const double *Ainv, const T *b, T *x, int tid) {
+    if (tid < kN0) {
+        const double *row = Ainv + tid * kN0;
         double a[kN0];
         T bv[kN0];
 #pragma unroll
@@ -145,7 +145,7 @@ __device__ void coarse_solve(const double *Ainv, const T *b, T *x) {
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < kN0; ++k) s += a[k] * double(bv[k]);
-        x[threadIdx.x] = T(s);
+        x[tid] = T(s);
     }
     __syncthreads();
 }
@@ -154,6 +154,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bool rhs_array, int out) {
     const int s = blockIdx.x;
     if (A.active && A.active[s] == 0) return;
+    const int tid = threadIdx.x;
     extern __shared__ unsigned char smem_raw[];
     T *const base = reinterpret_cast<T *>(smem_raw);
     const int top = A.top;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         if (k == top && A.top_from_k) {
             const T *K = A.Ktop + size_t(s) * nn;
 #pragma unroll 4
-            for (int c = threadIdx.x; c < nn; c += kThreads) {
+            for (int c = tid; c < nn; c += kThreads) {
                 const int i = c & (n - 1), j = c >> Lk.lg;
                 // the west and south neighbours' K, loaded without a branch (own K at an edge)
                 const T kc = K[c], kw = K[i > 0 ? c - 1 : c], ksn = K[j > 0 ? c - n : c];
@@ -202,11 +203,11 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             const T *fx = A.f[k].fx + size_t(s) * nn, *fy = A.f[k].fy + size_t(s) * nn;
             const T *fe = A.f[k].fxe + size_t(s) * n, *fn = A.f[k].fyn + size_t(s) * n;
 #pragma unroll 4
-            for (int c = threadIdx.x; c < nn; c += kThreads) {
+            for (int c = tid; c < nn; c += kThreads) {
                 Lk.fx[c] = fx[c];
                 Lk.fy[c] = fy[c];
             }
-            for (int c = threadIdx.x; c < n; c += kThreads) {
+            for (int c = tid; c < n; c += kThreads) {
                 Lk.fxe[c] = fe[c];
                 Lk.fyn[c] = fn[c];
             }
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         const Lv<T> Tp = lv(top);
         const int n = Tp.n, nn = n * n;
 #pragma unroll 4
-        for (int c = threadIdx.x; c < nn; c += kThreads) {
+        for (int c = tid; c < nn; c += kThreads) {
             const int i = c & (n - 1), j = c >> Tp.lg;
             if (rhs_array) {
                 Tp.b[c] = A.b[size_t(s) * nn + c];
@@ -249,16 +250,16 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         if (down) {
             if (k == 0) {
                 const Lv<T> L0 = lv(0);
-                coarse_solve(Ls, L0.b, L0.x);
+                coarse_solve(Ls, L0.b, L0.x, tid);
                 if (top == 0) break;
                 k = 1;
                 down = false;
                 continue;
             }
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
-            smooth(Lk, A.nu1);
+            smooth(Lk, A.nu1, tid);
             const int n = Lk.n, nc = n / 2;
-            for (int c = threadIdx.x; c < nc * nc; c += kThreads) {
+            for (int c = tid; c < nc * nc; c += kThreads) {
                 const int I = c & (nc - 1), J = c >> (Lk.lg - 1);
                 T acc = T(0);
                 for (int dj = 0; dj < 2; ++dj)
@@ -283,10 +284,10 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             }
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
             const int n = Lk.n, nc = n / 2;
-            for (int c = threadIdx.x; c < n * n; c += kThreads)
+            for (int c = tid; c < n * n; c += kThreads)
                 Lk.x[c] += prolong_at(Lc.x, nc, Lc.lg, c & (n - 1), c >> Lk.lg, dns);
             __syncthreads();
-            smooth(Lk, A.nu2);
+            smooth(Lk, A.nu2, tid);
             if (k == top) break;
             k = k + 1;
         }
