@@ -158,6 +158,11 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // east neighbours from LDS. FP64 reads them from the LDS ring (its
     // register rings leave no room).
     constexpr bool RC = sizeof(T) == 4;
+    // FP64: 1/diagonal recomputed in each half-sweep from the coefficient ring
+    // instead of being held in a ring of its own; the registers this frees keep
+    // the FP64 correction passes from spilling (the sum now starts from the
+    // faces as stored, so results move at the rounding level)
+    constexpr bool RI = sizeof(T) == 8;
     V2<T> hv[NH + 1];
 #pragma unroll
     for (int t = 0; t <= NH; ++t) hv[t] = V2<T>{T(0), T(0)};
