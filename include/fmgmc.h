@@ -55,7 +55,10 @@ enum {
 enum {
     FMGMC_FLAG_NOTCONV = 1,    /* a QoI stage stopped at max_cycles above rel_tol */
     FMGMC_FLAG_NONFINITE = 2,  /* non-finite residual or coefficient */
-    FMGMC_FLAG_WARM_REJECTED = 4  /* the learned start was worse than the FMG start and was discarded */
+    FMGMC_FLAG_WARM_REJECTED = 4, /* the learned start was worse than the FMG start and was discarded */
+    FMGMC_FLAG_FP64 = 8           /* FP32_IR: the sample missed rel_tol within max_cycles and was
+                                     solved again by the FP64 FMG pass, whose outputs (Q, cycles,
+                                     the other flag bits) replace the FP32_IR ones */
 };
 
 enum { FMGMC_COV_SEPARABLE_EXP = 0 };
@@ -162,6 +165,11 @@ int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, con
  *   q_fine, q_coarse  [n_samples] double
  *   cycles  [n_samples][2] int32: V-cycles at the coarse / fine QoI stage (nullable)
  *   flags   [n_samples] uint8, FMGMC_FLAG_* bits (nullable)
+ * FP32_IR: a finite sample that misses rel_tol within max_cycles is solved
+ * again by the FP64 FMG pass (same field and stopping rule; an FP64 context
+ * the library creates on first need, 64 samples at a time) and carries its
+ * outputs, with FMGMC_FLAG_FP64 set; ENOTCONV is reported only if that pass
+ * misses rel_tol too.
  * Returns OK, ENOTCONV or ENONFINITE (outputs written in all three cases),
  * or EINVAL / ENOMEM / EHIP.
  */

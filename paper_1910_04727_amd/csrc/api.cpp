@@ -30,6 +30,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -188,6 +189,11 @@ struct fmgmc_ctx {
     };
     bool prof = false;
     std::vector<Rec> prof_rec[FMGMC_PROF_KINDS];
+    // FP32_IR: FP64 context (same field, hierarchy and stopping rule) that
+    // re-solves the samples the mixed-precision form leaves unconverged;
+    // created on first use, shared by the per-level threads under fb_mu
+    fmgmc_ctx *fallback = nullptr;
+    std::mutex fb_mu;
 };
 
 namespace {
@@ -274,6 +280,10 @@ int alloc_constants(fmgmc_ctx *c) {
 }
 
 void free_ctx(fmgmc_ctx *c) {
+    if (c->fallback) {
+        fmgmc_destroy(c->fallback);
+        c->fallback = nullptr;
+    }
     for (auto &p : c->d_phi) dfree(p);
     c->d_phi.clear();
     dfree(c->d_ma); dfree(c->d_mb); dfree(c->d_sqrtlam);
@@ -708,6 +718,48 @@ struct DevGuard {
 };
 
 // One MLMC level on workspace W: chunks of at most tn.batch samples.
+// FP32_IR samples of a chunk that missed rel_tol within max_cycles (finite
+// ones) are solved again by the FP64 FMG pass on the same field; their Q,
+// cycles and flags are replaced in the caller's arrays (host or device) and
+// FMGMC_FLAG_FP64 is set. hf holds the chunk's flags on the host and is
+// updated. xdev: the chunk's coordinates on the device.
+int fp64_fallback(fmgmc_ctx *ctx, int level, int S, int64_t s0, const double *xdev, double *q_fine,
+                  double *q_coarse, int32_t *cycles, uint8_t *flags, std::vector<uint8_t> &hf) {
+    std::vector<int> bad;
+    for (int s = 0; s < S; ++s)
+        if ((hf[s] & FMGMC_FLAG_NOTCONV) && !(hf[s] & FMGMC_FLAG_NONFINITE)) bad.push_back(s);
+    if (bad.empty()) return FMGMC_OK;
+    std::lock_guard<std::mutex> lock(ctx->fb_mu);
+    if (!ctx->fallback) {
+        fmgmc_opts o = ctx->opts;
+        o.solver = FMGMC_SOLVER_FP64;
+        o.nu1 = std::min(o.nu1, 2);
+        o.nu2 = std::min(o.nu2, 2);
+        o.max_batch = 64;
+        o.fuse_cycles = 0;
+        TRY(fmgmc_create(&ctx->fallback, &ctx->field, &ctx->hier, &o, ctx->device));
+    }
+    const int M = ctx->table.M, nb = int(bad.size());
+    std::vector<double> xb(size_t(nb) * M), qf(nb), qc(nb);
+    std::vector<int32_t> cy(2 * size_t(nb));
+    std::vector<uint8_t> fl(nb);
+    for (int i = 0; i < nb; ++i)
+        FMGMC_HIP(hipMemcpy(xb.data() + size_t(i) * M, xdev + size_t(bad[i]) * M, M * sizeof(double),
+                            hipMemcpyDeviceToHost));
+    const int rc = fmgmc_solve_level(ctx->fallback, level, nb, xb.data(), qf.data(), qc.data(), cy.data(),
+                                     fl.data(), nullptr);
+    if (rc != FMGMC_OK && rc != FMGMC_ENOTCONV && rc != FMGMC_ENONFINITE) return rc;
+    for (int i = 0; i < nb; ++i) {
+        const int64_t g = s0 + bad[i];
+        hf[bad[i]] = uint8_t(fl[i] | FMGMC_FLAG_FP64 | (hf[bad[i]] & FMGMC_FLAG_WARM_REJECTED));
+        FMGMC_HIP(hipMemcpy(q_fine + g, &qf[i], sizeof(double), hipMemcpyDefault));
+        FMGMC_HIP(hipMemcpy(q_coarse + g, &qc[i], sizeof(double), hipMemcpyDefault));
+        if (cycles) FMGMC_HIP(hipMemcpy(cycles + 2 * g, &cy[2 * size_t(i)], 2 * sizeof(int32_t), hipMemcpyDefault));
+        if (flags) FMGMC_HIP(hipMemcpy(flags + g, &hf[bad[i]], 1, hipMemcpyDefault));
+    }
+    return FMGMC_OK;
+}
+
 int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n_samples, const double *xi,
                    double *q_fine, double *q_coarse, int32_t *cycles, uint8_t *flags, hipStream_t st,
                    bool *any_notconv, bool *any_nonfinite) {
@@ -769,6 +821,7 @@ int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n
         FMGMC_HIP(hipMemcpyAsync(hflags.data(), W.flags, S, hipMemcpyDeviceToHost, st));
         FMGMC_HIP(hipStreamSynchronize(st));
         if (flags && !fl_dev) std::memcpy(flags + s0, hflags.data(), S);
+        if (ir) TRY(fp64_fallback(ctx, level, S, s0, x, q_fine, q_coarse, cycles, flags, hflags));
         for (int s = 0; s < S; ++s) {
             *any_notconv |= (hflags[s] & FMGMC_FLAG_NOTCONV) != 0;
             *any_nonfinite |= (hflags[s] & FMGMC_FLAG_NONFINITE) != 0;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmgmc.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
-FLAG_NOTCONV, FLAG_NONFINITE = 1, 2
+FLAG_NOTCONV, FLAG_NONFINITE, FLAG_WARM_REJECTED, FLAG_FP64 = 1, 2, 4, 8
 SOLVERS = {"fp64": 0, "fp32_ir": 1}
 KL_PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp64_dense": 3}
 

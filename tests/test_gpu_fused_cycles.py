@@ -141,3 +141,34 @@ def test_fused_at_the_largest_grid():
     e = max(np.max(np.abs(qf - oqf) / np.abs(oqf)), np.max(np.abs(qc - oqc) / np.abs(oqc)))
     log(f"  vs oracle {e:.2e}; cycles {cyc.tolist()}")
     assert e <= 1e-8
+
+
+def test_unconverged_ir_samples_fall_back_to_fp64():
+    """FP32 cycles alone cannot take a stage to rel-res 1e-10 (their correction is limited by FP32
+    rounding), so with six FP32 cycles before the only refinement and max_cycles = 6 the FP32+IR
+    form leaves samples unconverged; each such sample is solved again by the FP64 FMG pass, whose
+    outputs it then carries, with FLAG_FP64 set."""
+    cfg = CFG2
+    level, S = 2, 12
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=1)
+    log(f"FP64 fallback: fp32_ir with inner_first = max_cycles = 6, n 128, S {S}")
+    with fmgmc.Context(**cfg, solver="fp32_ir", max_cycles=6, inner_first=6, w_max_n=32) as ctx:
+        rc, qf, qc, cyc, fl, _ = run(ctx, level, xi)
+    with fmgmc.Context(**cfg, solver="fp64", max_cycles=6, w_max_n=32) as c64:
+        rc64, qf64, qc64, cyc64, fl64, _ = run(c64, level, xi)
+    fb = (fl & fmgmc.FLAG_FP64) != 0
+    log(f"  fell back {fb.sum()}/{S}; rc {rc}; fp64 rc {rc64}")
+    assert fb.any()
+    assert np.array_equal(qf[fb], qf64[fb]) and np.array_equal(qc[fb], qc64[fb])
+    assert np.array_equal(cyc[fb], cyc64[fb]) and np.array_equal(fl[fb] & np.uint8(0xFF ^ fmgmc.FLAG_FP64), fl64[fb])
+    assert np.all((fl[~fb] & fmgmc.FLAG_NOTCONV) == 0)
+    assert (rc == fmgmc.OK) == (not np.any(fl & fmgmc.FLAG_NOTCONV))
+    # a sample the FP64 pass cannot finish either stays flagged, and the call reports it
+    with fmgmc.Context(**cfg, solver="fp32_ir", max_cycles=1, w_max_n=32) as ctx:
+        rc, qf, qc, cyc, fl, _ = run(ctx, level, xi[:3])
+    assert rc == fmgmc.ENOTCONV
+    assert np.all(fl & fmgmc.FLAG_NOTCONV) and np.all(fl & fmgmc.FLAG_FP64) and np.all(np.isfinite(qf))
+    # non-finite samples are not re-solved
+    with fmgmc.Context(**cfg, solver="fp32_ir", w_max_n=32) as ctx:
+        rc, qf, qc, cyc, fl, _ = run(ctx, level, xi[:3] * 1e3)
+    assert rc == fmgmc.ENONFINITE and np.all(fl & fmgmc.FLAG_NONFINITE) and not np.any(fl & fmgmc.FLAG_FP64)
