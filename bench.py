@@ -132,9 +132,16 @@ def cpu_baseline(xi, n_samples):
     t0 = time.perf_counter()
     O.solve_level(CFG["sigma2"], CFG["corr_len"], tab, N, LEVEL, sub, tol=1e-10, nthreads=threads)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(n_samples / dt, 3), "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_samples} of the 4096 samples at 512^2 (FP64 KL + FMG to 1e-10), "
-                      f"{dt:.1f} s wall on {threads} threads"}
+                      f"{dt:.1f} s wall on {threads} threads",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 # ----------------------------------------------------------------- reports
