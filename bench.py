@@ -410,8 +410,21 @@ def report_cfg4(torch, fmgmc, inputs, args):
     xo = xd[L - 1][:k].cpu().numpy()
     of, oc = _oracle_subset(cfg, L - 1, xo, 1e-10)
     est = fmgmc.estimate([o[0] for o in out], [o[1] for o in out])
+    # convergence factor per cycle of the same algorithm on this rough field:
+    # the oracle's residual history at both QoI stages of 4 samples at 256^2
+    from oracle import oracle as O
+    tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
+    fac = []
+    for x in xd[3][:4].cpu().numpy():
+        o = O.fmg_sample(O.field(256, cfg["corr_len"], tab, x), level=3, tol=1e-10, max_cycles=60, history=True)
+        for h in o["hist"]:
+            h = h[h > 1e-13]
+            fac += list(h[1:] / h[:-1])
+    vfac = {"max": round(float(max(fac)), 4), "geomean": round(float(np.exp(np.mean(np.log(fac)))), 4),
+            "n": 256, "samples": 4}
     return {"metric": "cfg4 uneven-size batched stress", "value": res["concurrent_autotuned"], "unit": "samples/s",
             "status": int(rc), "throughput": res, "autotuned_results_identical": bool(same), "levels": lv,
+            "cycle_factor_oracle_256": vfac,
             "estimate": est["mean"], "var_of_mean": est["var_of_mean"],
             "qf_1024_rel_err_vs_oracle": _rel(out[L - 1][0][:k].cpu().numpy(), of),
             "qc_1024_rel_err_vs_oracle": _rel(out[L - 1][1][:k].cpu().numpy(), oc),
