@@ -172,3 +172,28 @@ def test_unconverged_ir_samples_fall_back_to_fp64():
     with fmgmc.Context(**cfg, solver="fp32_ir", w_max_n=32) as ctx:
         rc, qf, qc, cyc, fl, _ = run(ctx, level, xi[:3] * 1e3)
     assert rc == fmgmc.ENONFINITE and np.all(fl & fmgmc.FLAG_NONFINITE) and not np.any(fl & fmgmc.FLAG_FP64)
+
+
+def test_fall_back_under_all_levels_at_once():
+    """The per-level host threads of solve_levels share the FP64 context of the fallback:
+    results and flags equal those of one level at a time."""
+    cfg = CFG2
+    ns = [10, 6]
+    xs = [inputs.mc_normals(n, cfg["n_modes"], config=2, level=l, purpose=1) for l, n in enumerate(ns)]
+    kw = dict(solver="fp32_ir", max_cycles=6, inner_first=6, w_max_n=32)
+    with fmgmc.Context(**cfg, **kw) as ctx:
+        one = [run(ctx, l, xs[l])[1:5] for l in range(2)]
+    with fmgmc.Context(**cfg, **kw) as ctx:
+        xd = [torch.from_numpy(x).cuda() for x in xs]
+        qf = [torch.zeros(n, dtype=torch.float64, device="cuda") for n in ns]
+        qc = [torch.zeros(n, dtype=torch.float64, device="cuda") for n in ns]
+        cy = [torch.zeros((n, 2), dtype=torch.int32, device="cuda") for n in ns]
+        fl = [torch.zeros(n, dtype=torch.uint8, device="cuda") for n in ns]
+        ctx.solve_levels(xd, qf, qc, cy, fl)
+        torch.cuda.synchronize()
+    for l in range(2):
+        f = fl[l].cpu().numpy()
+        log(f"  level {l}: fell back {int(((f & fmgmc.FLAG_FP64) != 0).sum())}/{ns[l]}")
+        assert np.any(f & fmgmc.FLAG_FP64)
+        assert np.array_equal(qf[l].cpu().numpy(), one[l][0]) and np.array_equal(qc[l].cpu().numpy(), one[l][1])
+        assert np.array_equal(cy[l].cpu().numpy(), one[l][2]) and np.array_equal(f, one[l][3])
