@@ -73,7 +73,8 @@ __device__ __forceinline__ void st2_nt(T *p, T a, T b) {
 
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T *red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    // butterfly over the wave's lanes of this workgroup (fewer than 64 for n < 128)
+    for (int o = min(32, int(blockDim.x) >> 1); o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
     if (l == 0) red[w] = v;

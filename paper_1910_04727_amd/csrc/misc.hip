@@ -99,7 +99,8 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
         for (int u = 0; u < D; ++u)
             if (F0 + u <= n) step(F0 + u, u, std::true_type{});
     }
-    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
+    // butterfly over the wave's lanes of this workgroup (n lanes when n < 64)
+    for (int o = min(32, n >> 1); o > 0; o >>= 1) rr += __shfl_xor(rr, o);
     __syncthreads();
     if ((i & 63) == 0) red[i >> 6] = rr;
     __syncthreads();
