@@ -41,8 +41,13 @@ def log(*a):
 WEIGHTS = os.path.join(ROOT, "paper_1910_04727_amd", "weights", "cnn_cfg2.bin")
 
 
-def run_form(torch, fmgmc, xi_dev, form, args):
-    """form: fp32_ir, fp64, or nn_warm (fp32_ir started from the trained network on 256^2 and 512^2)."""
+def run_form(torch, fmgmc, xi_dev, form, args, tol=None, steps=None, warmup=None, separate_coarse=False):
+    """form: fp32_ir, fp64, or nn_warm (fp32_ir started from the trained network on 256^2 and 512^2).
+    tol / steps / warmup default to the command line's; separate_coarse: the standard-MLMC
+    comparator (Q^c from its own FMG solve on 256^2)."""
+    tol = args.tol if tol is None else tol
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     solver = "fp32_ir" if form == "nn_warm" else form
     S = xi_dev.shape[0]
     qf = torch.zeros(S, dtype=torch.float64, device="cuda")
@@ -50,9 +55,10 @@ def run_form(torch, fmgmc, xi_dev, form, args):
     cyc = torch.zeros((S, 2), dtype=torch.int32, device="cuda")
     fl = torch.zeros(S, dtype=torch.uint8, device="cuda")
     nu1, nu2 = (int(v) for v in args.nu.split(",")) if solver == "fp32_ir" else (2, 2)
-    ctx = fmgmc.Context(**CFG, solver=solver, rel_tol=args.tol, max_batch=args.batch,
+    ctx = fmgmc.Context(**CFG, solver=solver, rel_tol=tol, max_batch=args.batch,
                         inner_cycles=args.inner, max_cycles=60, nu1=nu1, nu2=nu2, w_max_n=args.wmax,
-                        inner_first=args.inner_first, fuse_cycles=not args.no_fuse)
+                        inner_first=args.inner_first, fuse_cycles=not args.no_fuse,
+                        separate_coarse=separate_coarse)
     net = None
     if form == "nn_warm":
         net = fmgmc.Cnn(path=WEIGHTS)
@@ -63,15 +69,16 @@ def run_form(torch, fmgmc, xi_dev, form, args):
         est = fmgmc.estimate([qf], [qc])
         return rc, est
 
-    for w in range(args.warmup):
+    tag = f"{form} tol {tol:g}" + (" separate coarse" if separate_coarse else "")
+    for w in range(warmup):
         step()
-        log(f"[{form}] warmup {w + 1}/{args.warmup} done")
+        log(f"[{tag}] warmup {w + 1}/{warmup} done")
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         rc, est = step()
-        log(f"[{form}] step {k + 1}/{args.steps} done")
+        log(f"[{tag}] step {k + 1}/{steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
@@ -79,20 +86,24 @@ def run_form(torch, fmgmc, xi_dev, form, args):
     ctx.close()
     if net is not None:
         net.close()
-    dt = (t1 - t0) / args.steps
+    dt = (t1 - t0) / steps
     c = cyc.cpu().numpy()
     return dict(samples_per_s=S / dt, ms_per_step=1e3 * dt, rc=int(rc),
                 cycles_coarse_mean=float(c[:, 0].mean()), cycles_fine_mean=float(c[:, 1].mean()),
-                cycles_fine_max=int(c[:, 1].max()), flags=int(((fl.cpu().numpy() & 3) != 0).sum()),
-                warm_rejected=int(((fl.cpu().numpy() & 4) != 0).sum()),
+                cycles_fine_max=int(c[:, 1].max()), flags=int(((fl.cpu().numpy() & 7) != 0).sum()),
+                warm_rejected=int(((fl.cpu().numpy() & fmgmc.FLAG_WARM_REJECTED) != 0).sum()),
                 estimate=dict(mean_y=est["levels"][0]["mean_y"], var_y=est["levels"][0]["var_y"]),
-                prof=prof, qf=qf.cpu().numpy(), qc=qc.cpu().numpy())
+                prof=prof, qf=qf.cpu().numpy(), qc=qc.cpu().numpy(), cycles=c)
 
 
 # Measured HBM traffic / algorithmic bytes of the dominant kernels, from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
-# (profiles/hbm_traffic_512.md). None once a kernel changes after measurement.
+# (profiles/hbm_traffic_512.md; taken offline, not in this run). None once a
+# kernel changes after measurement.
 TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000, "fused": 1.000}
+TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE passes over the same launch, calibrated on a plain "
+                  "copy (profiles/hbm_traffic_512.md); taken offline, not in this run")
+STENCIL_TARGET = 0.60  # fraction of the HBM peak the stencil passes aim for
 
 
 def roofline(form, steps):
@@ -108,8 +119,12 @@ def roofline(form, steps):
     traffic = None if ratio is None else round(ratio * alg / n / 1e9, 4)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "GB per launch",
+            "traffic_source": TRAFFIC_SOURCE if traffic is not None else None,
             "kernel": kind, "avg_launch_us": round(1e3 * ms / n, 2), "launches": n,
-            "alg_bytes_per_launch": alg / n}
+            "alg_bytes_per_launch": alg / n,
+            "stencil_passes_512": pass_table(form),
+            "stencil_passes_below_target": sorted(k for k, v in pass_table(form).items()
+                                                  if v["frac"] < STENCIL_TARGET)}
 
 
 def pass_table(form):
@@ -119,18 +134,22 @@ def pass_table(form):
     for kind in ("pre", "post", "ir", "fused"):
         ms, n, alg = form["prof"][kind]
         if n:
+            gbs = alg / (ms * 1e-3) / 1e9
             out[kind] = {"launches": n, "avg_launch_us": round(1e3 * ms / n, 2),
-                         "achieved_gbs": round(alg / (ms * 1e-3) / 1e9, 1)}
+                         "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     return out
 
 
-def cpu_baseline(xi, n_samples):
+def cpu_baseline(xi, n_samples, tol, wmax):
+    """The oracle timed on the host cores on the first n_samples samples; also
+    returns its Q^f, Q^c and cycle counts (the reference of the accuracy records)."""
     from oracle import oracle as O
     threads = O.max_threads()
     tab = O.kl_table(CFG["sigma2"], CFG["corr_len"], CFG["n_modes"])
     sub = xi[:n_samples]
     t0 = time.perf_counter()
-    O.solve_level(CFG["sigma2"], CFG["corr_len"], tab, N, LEVEL, sub, tol=1e-10, nthreads=threads)
+    oqf, oqc, ocyc, _ = O.solve_level(CFG["sigma2"], CFG["corr_len"], tab, N, LEVEL, sub, tol=tol,
+                                      nthreads=threads, wmax=wmax)
     dt = time.perf_counter() - t0
     model = ""
     try:
@@ -139,9 +158,29 @@ def cpu_baseline(xi, n_samples):
     except OSError:
         pass
     return {"value": round(n_samples / dt, 3), "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_samples} of the 4096 samples at 512^2 (FP64 KL + FMG to 1e-10), "
+            "sample": f"{n_samples} of the 4096 samples at 512^2 (FP64 KL + FMG to {tol:g}), "
                       f"{dt:.1f} s wall on {threads} threads",
-            "cpu_model": model, "host_cpus": os.cpu_count()}
+            "cpu_model": model, "host_cpus": os.cpu_count()}, (oqf, oqc, ocyc)
+
+
+def oracle_ref(xi, n_samples, tol, wmax):
+    """Oracle Q^f, Q^c on the first n_samples samples (untimed reference)."""
+    from oracle import oracle as O
+    tab = O.kl_table(CFG["sigma2"], CFG["corr_len"], CFG["n_modes"])
+    oqf, oqc, ocyc, _ = O.solve_level(CFG["sigma2"], CFG["corr_len"], tab, N, LEVEL, xi[:n_samples], tol=tol,
+                                      nthreads=O.max_threads(), wmax=wmax)
+    return oqf, oqc, ocyc
+
+
+def qoi_err(form, ref):
+    """Per-sample relative QoI error of a form against the oracle on the reference samples."""
+    oqf, oqc, ocyc = ref
+    k = len(oqf)
+    ef = np.abs(form["qf"][:k] - oqf) / np.abs(oqf)
+    ec = np.abs(form["qc"][:k] - oqc) / np.abs(oqc)
+    return {"samples": int(k), "qf_max": float(ef.max()), "qf_median": float(np.median(ef)),
+            "qc_max": float(ec.max()), "qc_median": float(np.median(ec)),
+            "same_cycles": int(np.all(form["cycles"][:k] == ocyc, axis=1).sum())}
 
 
 # ----------------------------------------------------------------- reports
@@ -480,7 +519,7 @@ def report_cfg5(torch, fmgmc, inputs, args):
         "cycles_plain": [round(float(x), 4) for x in p[2].mean(0)],
         "cycles_warm": [round(float(x), 4) for x in w[2].mean(0)],
         "cycles_saved": [round(float(x), 4) for x in p[2].mean(0) - w[2].mean(0)],
-        "warm_rejected": int(((w[3] & 4) != 0).sum()), "flagged": int((w[3] & 3).sum()),
+        "warm_rejected": int(((w[3] & fmgmc.FLAG_WARM_REJECTED) != 0).sum()), "flagged": int((w[3] & 3).sum()),
         "samples_per_s_plain": round(S / p[4], 1), "samples_per_s_warm": round(S / w[4], 1),
         "cnn_ms_per_solve": round(cms, 3), "cnn_tflops": round(cfl / (cms * 1e-3) / 1e12, 2) if cn else None,
         "estimate_plain": ep, "estimate_warm": ew, "estimate_rel_diff": abs(ew - ep) / abs(ep),
@@ -639,6 +678,11 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cnn-train", type=int, default=16384, help="cfg5: level-4 training samples")
+    ap.add_argument("--acc-tol", type=float, default=1e-12,
+                    help="tolerance of the accuracy record (every form against the oracle; 0 = skip)")
+    ap.add_argument("--acc-steps", type=int, default=4, help="timed steps per form of the accuracy record")
+    ap.add_argument("--saving-steps", type=int, default=3,
+                    help="timed steps of the standard-MLMC comparator (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -718,9 +762,47 @@ def main():
         a, b = forms["fp32_ir"], forms["fp64"]
         out["forms"]["ir_vs_fp64_speedup"] = round(a["samples_per_s"] / b["samples_per_s"], 3)
         out["forms"]["ir_vs_fp64_max_rel_qf_diff"] = float(np.max(np.abs(a["qf"] - b["qf"]) / np.abs(b["qf"])))
+    # the paper's only performance statement, as context (not a target)
+    out["paper_context"] = {
+        "saving_from_qc_reuse": 0.2,
+        "statement": "FMG-MLMC saves about 20% of the cost of MLMC asymptotically by taking Q^c_l from the FMG "
+                     "pass that yields Q^f_l (Abstract; closed form 1/(1+2^gamma), gamma = 2 in 2-D); "
+                     "no hardware, precision or timing is given",
+    }
+    if args.saving_steps and head == "fp32_ir":
+        sep = run_form(torch, fmgmc, xi_dev, "fp32_ir", args, steps=args.saving_steps, warmup=1,
+                       separate_coarse=True)
+        out["paper_context"]["measured_saving_vs_standard_mlmc"] = {
+            "value": round(1.0 - H["ms_per_step"] / sep["ms_per_step"], 4),
+            "standard_mlmc_ms_per_step": round(sep["ms_per_step"], 2), "fmg_mlmc_ms_per_step": round(H["ms_per_step"], 2),
+            "note": "FP32+IR at rel-res 1e-10 on both QoI stages; standard MLMC solves Q^c with its own FMG pass "
+                    "to 256^2 (same injected coefficients)"}
     if not args.no_cpu:
         log(f"cpu baseline: oracle on {args.cpu_samples} samples")
-        out["cpu_baseline"] = cpu_baseline(xi, args.cpu_samples)
+        out["cpu_baseline"], ref10 = cpu_baseline(xi, args.cpu_samples, args.tol, args.wmax)
+        for k, f in forms.items():
+            out["forms"][k][f"qoi_vs_oracle_at_{args.tol:g}"] = qoi_err(f, ref10)
+        if args.acc_tol > 0:
+            # the mixed-precision bar at one tolerance: each form and the oracle driven to acc_tol
+            log(f"accuracy record: oracle at {args.acc_tol:g} on {args.cpu_samples} samples")
+            ref = oracle_ref(xi, args.cpu_samples, args.acc_tol, args.wmax)
+            rec = {"tol": args.acc_tol, "reference": f"oracle at rel-res {args.acc_tol:g} on the cpu_baseline samples",
+                   "bar": 1e-8, "forms": {}}
+            for k in forms:
+                f = run_form(torch, fmgmc, xi_dev, k, args, tol=args.acc_tol, steps=args.acc_steps, warmup=1)
+                e = qoi_err(f, ref)
+                rec["forms"][k] = {"samples_per_s": round(f["samples_per_s"], 2),
+                                   "cycles_mean": [round(f["cycles_coarse_mean"], 3), round(f["cycles_fine_mean"], 3)],
+                                   "flagged_samples": f["flags"], "qoi_vs_oracle": e,
+                                   "meets_bar": bool(max(e["qf_max"], e["qc_max"]) <= 1e-8)}
+            if "fp32_ir" in rec["forms"] and "fp64" in rec["forms"]:
+                rec["ir_vs_fp64_speedup"] = round(rec["forms"]["fp32_ir"]["samples_per_s"] /
+                                                  rec["forms"]["fp64"]["samples_per_s"], 3)
+            rec["note"] = ("the headline value is measured at rel-res 1e-10; there the stopping rule itself leaves "
+                           "QoI differences up to ~3e-7 between any two solver forms at 512^2 (each stops at a "
+                           "different iterate of the same discrete problem), so the 1e-8 bar is shown with both "
+                           "sides driven to this tolerance")
+            out["accuracy_at_tight_tol"] = rec
     print(json.dumps(out), flush=True)
 
 

@@ -55,10 +55,10 @@ enum {
 enum {
     FMGMC_FLAG_NOTCONV = 1,    /* a QoI stage stopped at max_cycles above rel_tol */
     FMGMC_FLAG_NONFINITE = 2,  /* non-finite residual or coefficient */
-    FMGMC_FLAG_WARM_REJECTED = 4, /* the learned start was worse than the FMG start and was discarded */
-    FMGMC_FLAG_FP64 = 8           /* FP32_IR: the sample missed rel_tol within max_cycles and was
+    FMGMC_FLAG_FP64 = 4,          /* FP32_IR: the sample missed rel_tol within max_cycles and was
                                      solved again by the FP64 FMG pass, whose outputs (Q, cycles,
                                      the other flag bits) replace the FP32_IR ones */
+    FMGMC_FLAG_WARM_REJECTED = 8  /* the learned start was worse than the FMG start and was discarded */
 };
 
 enum { FMGMC_COV_SEPARABLE_EXP = 0 };
@@ -122,7 +122,18 @@ typedef struct {
                               once instead of twice); needs nu1 + nu2 <= 4. 0 = separate
                               passes. Converged results agree to the stopping tolerance; the
                               FP32 iterates may differ in rounding. */
+    int32_t warm;          /* FMGMC_WARM_NONE, or FMGMC_WARM_CNN: fmgmc_create loads the network
+                              file cnn_weights into a network the context owns and warm-starts
+                              every QoI stage with n >= warm_min_n from it (as
+                              fmgmc_set_warm_start); needs FMGMC_SOLVER_FP32_IR and Case II */
+    int32_t warm_min_n;    /* smallest QoI stage grid the network starts (0 = 256) */
+    const char *cnn_weights; /* network file (fmgmc_cnn_save format) for FMGMC_WARM_CNN, else NULL */
+    const char *tune_cache;  /* NULL, or a schedule file: fmgmc_create reads the per-level schedules
+                                from it when it exists and was written for the same hierarchy and
+                                solver; fmgmc_autotune rewrites it with every level's schedule */
 } fmgmc_opts;
+
+enum { FMGMC_WARM_NONE = 0, FMGMC_WARM_CNN = 1 };
 
 typedef struct fmgmc_ctx fmgmc_ctx;
 
@@ -211,7 +222,7 @@ int fmgmc_autotune(fmgmc_ctx *ctx, int32_t level, int64_t n_pilot, const double 
                    int32_t *params);
 int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params);
 
-/* Per-level statistics filled by fmgmc_estimate. */
+/* Per-level statistics of the estimators. */
 typedef struct {
     int64_t n;        /* samples */
     double mean_y;    /* mean of Y = Q^f - Q^c (the level term of Eq. (3)) */
@@ -221,20 +232,36 @@ typedef struct {
     double mean_qc;
 } fmgmc_level_est;
 
+#define FMGMC_MAX_LEVELS 16
+/* MLMC / MLQMC estimate over up to FMGMC_MAX_LEVELS levels. */
+typedef struct {
+    int32_t n_levels;                          /* levels filled in `level` */
+    fmgmc_level_est level[FMGMC_MAX_LEVELS];
+    double mean;                               /* sum_l mean_y[l] (Eq. (5)'s estimator) */
+    double var_of_mean;                        /* its variance (Eq. (4)-(5); Section 2.4 for RQMC) */
+} fmgmc_est;
+
 /*
- * MLMC / MLQMC estimator (Section 2.1 Eqs. (2)-(5), Section 2.4) on the
- * device with compensated (Neumaier) sums in a fixed order.
+ * MLMC / MLQMC estimator (Section 2.1 Eqs. (2)-(5), Section 2.4) with
+ * compensated (Neumaier) sums in a fixed order, computed on the device.
  *   qf[l], qc[l]: n[l] samples of level l (host or device).
  *   n_shifts == 1: Monte Carlo; var_y is the sample variance of Y_l and
- *     *var_of_mean = sum_l var_y[l] / n[l].
- *   n_shifts  > 1: randomised QMC, samples grouped shift-major
- *     [shift][point]; mean_y is the mean of the per-shift means and var_y is
- *     sum_r (Ybar_r - mean_y)^2 / (R (R - 1)); *var_of_mean = sum_l var_y[l].
- *   levels[l] receives the per-level numbers; *mean = sum_l mean_y[l].
+ *     var_of_mean = sum_l var_y[l] / n[l].
+ *   n_shifts  > 1 (at most 4096): randomised QMC, samples grouped shift-major
+ *     [shift][point] (n[l] a multiple of n_shifts); mean_y is the mean of the
+ *     per-shift means and var_y is sum_r (Ybar_r - mean_y)^2 / (R (R - 1));
+ *     var_of_mean = sum_l var_y[l].
+ * fmgmc_estimate fills the aggregate *out (n_lev <= FMGMC_MAX_LEVELS) and runs
+ * on the null stream. fmgmc_estimate_levels writes levels[l] (n_lev entries,
+ * nullable), *mean and *var_of_mean (nullable) and runs on `stream`; both
+ * return after the results are on the host. Errors: EINVAL (sizes, NULL
+ * arrays), ENOMEM, EHIP.
  */
 int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf,
-                   const double *const *qc, int32_t n_shifts, fmgmc_level_est *levels,
-                   double *mean, double *var_of_mean, void *stream);
+                   const double *const *qc, int32_t n_shifts, fmgmc_est *out);
+int fmgmc_estimate_levels(int32_t n_lev, const int64_t *n, const double *const *qf,
+                          const double *const *qc, int32_t n_shifts, fmgmc_level_est *levels,
+                          double *mean, double *var_of_mean, void *stream);
 
 /*
  * Host-only (no device needed): the KL mode table of fmgmc_create for the

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <functional>
 #include <map>
 #include <memory>
@@ -180,8 +181,10 @@ struct fmgmc_ctx {
     Work main;                                  // finest-level workspace (fmgmc_solve_level)
     std::vector<std::unique_ptr<Work>> lev;     // per-level workspaces (fmgmc_solve_levels)
     std::vector<Tune> tune;                     // per MLMC level
-    const fmgmc_cnn *warm = nullptr;            // learned warm start (not owned)
+    const fmgmc_cnn *warm = nullptr;            // learned warm start
     int warm_min_n = 256;
+    fmgmc_cnn *owned_warm = nullptr;            // network loaded from opts.cnn_weights (owned)
+    std::string tune_path;                      // opts.tune_cache ("" = none)
     // measurement hooks
     struct Rec {
         hipEvent_t a, b;
@@ -280,6 +283,10 @@ int alloc_constants(fmgmc_ctx *c) {
 }
 
 void free_ctx(fmgmc_ctx *c) {
+    if (c->owned_warm) {
+        fmgmc_cnn_destroy(c->owned_warm);
+        c->owned_warm = nullptr;
+    }
     if (c->fallback) {
         fmgmc_destroy(c->fallback);
         c->fallback = nullptr;
@@ -703,7 +710,44 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
     if (o->solver == FMGMC_SOLVER_FP32_IR && h->n0 < 8) return FMGMC_EINVAL;  // QoI stages need n >= 8
     if (o->max_batch < 0 || o->w_max_n < 0 || o->separate_coarse < 0 || o->separate_coarse > 1) return FMGMC_EINVAL;
     if (o->fuse_cycles < 0 || o->fuse_cycles > 1) return FMGMC_EINVAL;
+    if (o->warm != FMGMC_WARM_NONE && o->warm != FMGMC_WARM_CNN) return FMGMC_EINVAL;
+    if (o->warm == FMGMC_WARM_CNN &&
+        (o->solver != FMGMC_SOLVER_FP32_IR || h->boundary != FMGMC_BC_MIXED || !o->cnn_weights))
+        return FMGMC_EINVAL;
+    if (o->warm_min_n != 0 && o->warm_min_n < 16) return FMGMC_EINVAL;
     return FMGMC_OK;
+}
+
+// Schedule file: a header naming the hierarchy and solver it was measured for,
+// then one line per tuned level: "level check_every graphs batch".
+std::string tune_header(const fmgmc_ctx *c) {
+    char b[160];
+    std::snprintf(b, sizeof(b), "fmgmc-schedule 1 levels %d n0 %d solver %d boundary %d", c->hier.n_levels,
+                  c->hier.n0, c->opts.solver, c->hier.boundary);
+    return b;
+}
+
+void read_tune_cache(fmgmc_ctx *c) {
+    if (c->tune_path.empty()) return;
+    std::ifstream f(c->tune_path);
+    std::string head;
+    if (!f || !std::getline(f, head) || head != tune_header(c)) return;
+    int l, G, gr, b;
+    while (f >> l >> G >> gr >> b)
+        if (l >= 0 && l < c->hier.n_levels && G >= 1 && (gr == 0 || gr == 1) && b >= 0) c->tune[l] = Tune{G, gr, b};
+}
+
+int write_tune_cache(const fmgmc_ctx *c) {
+    if (c->tune_path.empty()) return FMGMC_OK;
+    std::ofstream f(c->tune_path, std::ios::trunc);
+    if (!f) {
+        set_error("cannot write the schedule file " + c->tune_path);
+        return FMGMC_EINVAL;
+    }
+    f << tune_header(c) << "\n";
+    for (int l = 0; l < c->hier.n_levels; ++l)
+        f << l << " " << c->tune[l].check_every << " " << c->tune[l].graphs << " " << c->tune[l].batch << "\n";
+    return f.good() ? FMGMC_OK : FMGMC_EINVAL;
 }
 
 struct DevGuard {
@@ -737,6 +781,9 @@ int fp64_fallback(fmgmc_ctx *ctx, int level, int S, int64_t s0, const double *xd
         o.nu2 = std::min(o.nu2, 2);
         o.max_batch = 64;
         o.fuse_cycles = 0;
+        o.warm = FMGMC_WARM_NONE;
+        o.cnn_weights = nullptr;
+        o.tune_cache = nullptr;
         TRY(fmgmc_create(&ctx->fallback, &ctx->field, &ctx->hier, &o, ctx->device));
     }
     const int M = ctx->table.M, nb = int(bad.size());
@@ -865,6 +912,31 @@ int level_work(fmgmc_ctx *c, int level, Work **out) {
     return FMGMC_OK;
 }
 
+// Combines the per-level results of the estimator reduction (h: mean_y, var_y,
+// mean_qf, var_qf, mean_qc) into the level records and the MLMC sum (Eq. (5))
+// with its variance; the sum over the levels is compensated (Neumaier).
+struct EstAcc {
+    double total = 0.0, totc = 0.0, var = 0.0;
+    void add(int l, int64_t n, int n_shifts, const double *h, fmgmc_level_est *levels) {
+        if (levels) {
+            levels[l].n = n;
+            levels[l].mean_y = h[0];
+            levels[l].var_y = h[1];
+            levels[l].mean_qf = h[2];
+            levels[l].var_qf = h[3];
+            levels[l].mean_qc = h[4];
+        }
+        const double tt = total + h[0];
+        totc += (std::fabs(total) >= std::fabs(h[0])) ? (total - tt) + h[0] : (h[0] - tt) + total;
+        total = tt;
+        var += (n_shifts > 1) ? h[1] : h[1] / double(n);
+    }
+    void finish(double *mean, double *var_of_mean) const {
+        if (mean) *mean = total + totc;
+        if (var_of_mean) *var_of_mean = var;
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -898,6 +970,9 @@ int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hi
     c->device = device;
     if (c->opts.inner_cycles < 1) c->opts.inner_cycles = 1;
     if (c->opts.inner_first < 0) c->opts.inner_first = 0;
+    if (opts->tune_cache) c->tune_path = opts->tune_cache;
+    c->opts.tune_cache = nullptr;  // no caller pointer is kept
+    c->opts.cnn_weights = nullptr;
     int rc = build_mode_table(field->sigma2, field->corr_len, field->n_modes, c->table);
     if (rc != FMGMC_OK) {
         set_error("fmgmc_create: mode table");
@@ -914,10 +989,16 @@ int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hi
     c->main.profile = true;
     rc = alloc_constants(c.get());
     if (rc == FMGMC_OK) rc = alloc_work(c.get(), c->main, opts->max_batch > 0 ? opts->max_batch : 1024, nf);
+    if (rc == FMGMC_OK && opts->warm == FMGMC_WARM_CNN) {
+        rc = fmgmc_cnn_create(&c->owned_warm, 0, device);
+        if (rc == FMGMC_OK) rc = fmgmc_cnn_load(c->owned_warm, opts->cnn_weights);
+        if (rc == FMGMC_OK) rc = fmgmc_set_warm_start(c.get(), c->owned_warm, opts->warm_min_n > 0 ? opts->warm_min_n : 256);
+    }
     if (rc != FMGMC_OK) {
         free_ctx(c.get());
         return rc;
     }
+    read_tune_cache(c.get());
     *out = c.release();
     return FMGMC_OK;
 }
@@ -1169,7 +1250,7 @@ int fmgmc_autotune(fmgmc_ctx *ctx, int32_t level, int64_t n_pilot, const double 
         params[1] = best.graphs;
         params[2] = best.batch;
     }
-    return FMGMC_OK;
+    return write_tune_cache(ctx);
 }
 
 int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params) {
@@ -1278,23 +1359,36 @@ int fmgmc_cnn_train(fmgmc_ctx *ctx, fmgmc_cnn *cnn, int32_t level, int64_t n_sam
 }
 
 int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf, const double *const *qc,
-                   int32_t n_shifts, fmgmc_level_est *levels, double *mean, double *var_of_mean, void *stream) {
-    if (n_lev < 1 || !n || !qf || !qc || n_shifts < 1 || n_shifts > 4096) {
+                   int32_t n_shifts, fmgmc_est *out) {
+    if (!out || n_lev < 1 || n_lev > FMGMC_MAX_LEVELS) {
+        set_error("fmgmc_estimate: bad arguments (out NULL or n_lev outside 1..FMGMC_MAX_LEVELS)");
+        return FMGMC_EINVAL;
+    }
+    fmgmc_est e{};
+    e.n_levels = n_lev;
+    TRY(fmgmc_estimate_levels(n_lev, n, qf, qc, n_shifts, e.level, &e.mean, &e.var_of_mean, nullptr));
+    *out = e;
+    return FMGMC_OK;
+}
+
+int fmgmc_estimate_levels(int32_t n_lev, const int64_t *n, const double *const *qf, const double *const *qc,
+                          int32_t n_shifts, fmgmc_level_est *levels, double *mean, double *var_of_mean,
+                          void *stream) {
+    if (n_lev < 1 || !n || !qf || !qc || n_shifts < 1 || n_shifts > kEstMaxShifts) {
         set_error("fmgmc_estimate: bad arguments");
         return FMGMC_EINVAL;
     }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    double *dout = nullptr, *dscr = nullptr;
-    TRY(dalloc(&dout, 5));
-    TRY(dalloc(&dscr, 4096));
-    double total = 0.0, totc = 0.0, var = 0.0;  // compensated over levels
-    int rc = FMGMC_OK;
-    for (int l = 0; l < n_lev && rc == FMGMC_OK; ++l) {
+    for (int l = 0; l < n_lev; ++l)
         if (n[l] < 1 || !qf[l] || !qc[l] || (n_shifts > 1 && (n[l] % n_shifts) != 0)) {
             set_error("fmgmc_estimate: bad level sizes");
-            rc = FMGMC_EINVAL;
-            break;
+            return FMGMC_EINVAL;
         }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double *dout = nullptr, *dscr = nullptr;
+    int rc = dalloc(&dout, 5);
+    if (rc == FMGMC_OK) rc = dalloc(&dscr, kEstMaxShifts);
+    EstAcc acc;
+    for (int l = 0; l < n_lev && rc == FMGMC_OK; ++l) {
         const double *f = qf[l], *cc = qc[l];
         double *tf = nullptr, *tc = nullptr;
         if (!is_device_ptr(f)) {
@@ -1322,24 +1416,12 @@ int fmgmc_estimate(int32_t n_lev, const int64_t *n, const double *const *qf, con
         dfree(tf);
         dfree(tc);
         if (rc != FMGMC_OK) break;
-        if (levels) {
-            levels[l].n = n[l];
-            levels[l].mean_y = h[0];
-            levels[l].var_y = h[1];
-            levels[l].mean_qf = h[2];
-            levels[l].var_qf = h[3];
-            levels[l].mean_qc = h[4];
-        }
-        const double tt = total + h[0];  // Neumaier over the (few) levels
-        totc += (std::fabs(total) >= std::fabs(h[0])) ? (total - tt) + h[0] : (h[0] - tt) + total;
-        total = tt;
-        var += (n_shifts > 1) ? h[1] : h[1] / double(n[l]);
+        acc.add(l, n[l], n_shifts, h, levels);
     }
     dfree(dout);
     dfree(dscr);
     if (rc != FMGMC_OK) return rc;
-    if (mean) *mean = total + totc;
-    if (var_of_mean) *var_of_mean = var;
+    acc.finish(mean, var_of_mean);
     return FMGMC_OK;
 }
 

@@ -183,6 +183,8 @@ int launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
 
 // estimators: compensated sums in a fixed order
 int launch_level_reduce(const double *qf, const double *qc, int64_t n, int nshift, double *out,
-                        double *scratch, hipStream_t st);
+                        double *shift_means, hipStream_t st);
+// largest number of RQMC shifts the estimator reduction takes
+constexpr int kEstMaxShifts = 4096;
 
 }  // namespace fmgmc

@@ -378,14 +378,15 @@ int launch_fill_f64(double *p, double v, int64_t n, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
-int launch_level_reduce(const double *qf, const double *qc, int64_t n, int nshift, double *out, double *scratch,
-                        hipStream_t st) {
+int launch_level_reduce(const double *qf, const double *qc, int64_t n, int nshift, double *out,
+                        double *shift_means, hipStream_t st) {
     if (n <= 0 || nshift < 1 || (nshift > 1 && n % nshift != 0)) {
         set_error("launch_level_reduce: bad sizes");
         return FMGMC_EINVAL;
     }
-    hipLaunchKernelGGL(k_level_reduce, dim3(1), dim3(RT), 0, st, qf, qc, n, nshift, out, scratch);
+    hipLaunchKernelGGL(k_level_reduce, dim3(1), dim3(RT), 0, st, qf, qc, n, nshift, out, shift_means);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
+
 
 }  // namespace fmgmc

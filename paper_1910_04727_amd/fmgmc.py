@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmgmc.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
-FLAG_NOTCONV, FLAG_NONFINITE, FLAG_WARM_REJECTED, FLAG_FP64 = 1, 2, 4, 8
+FLAG_NOTCONV, FLAG_NONFINITE, FLAG_FP64, FLAG_WARM_REJECTED = 1, 2, 4, 8
 SOLVERS = {"fp64": 0, "fp32_ir": 1}
 KL_PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp64_dense": 3}
 
@@ -41,12 +41,22 @@ class Opts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("kl_prec", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("inner_cycles", C.c_int32),
                 ("max_batch", C.c_int32), ("w_max_n", C.c_int32), ("rel_tol", C.c_double),
-                ("inner_first", C.c_int32), ("separate_coarse", C.c_int32), ("fuse_cycles", C.c_int32)]
+                ("inner_first", C.c_int32), ("separate_coarse", C.c_int32), ("fuse_cycles", C.c_int32),
+                ("warm", C.c_int32), ("warm_min_n", C.c_int32), ("cnn_weights", C.c_char_p),
+                ("tune_cache", C.c_char_p)]
 
 
 class LevelEst(C.Structure):
     _fields_ = [("n", C.c_int64), ("mean_y", C.c_double), ("var_y", C.c_double),
                 ("mean_qf", C.c_double), ("var_qf", C.c_double), ("mean_qc", C.c_double)]
+
+
+MAX_LEVELS = 16
+
+
+class Est(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("level", LevelEst * MAX_LEVELS), ("mean", C.c_double),
+                ("var_of_mean", C.c_double)]
 
 
 class FmgmcError(RuntimeError):
@@ -65,7 +75,8 @@ _SIGS = {
     "fmgmc_kl_modes": (C.c_int, [C.c_double, C.c_double, C.c_int32, _VP, _VP, _VP]),
     "fmgmc_synthesize_field": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP]),
     "fmgmc_solve_level": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
-    "fmgmc_estimate": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "fmgmc_estimate": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, C.POINTER(Est)]),
+    "fmgmc_estimate_levels": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "fmgmc_solve_levels": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fmgmc_autotune": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP]),
     "fmgmc_set_schedule": (C.c_int, [_VP, C.c_int32, _VP]),
@@ -150,7 +161,8 @@ class Context:
     def __init__(self, sigma2, corr_len, n_modes, n_levels, n0, solver="fp64", kl_prec="fp64",
                  nu1=2, nu2=2, max_cycles=50, inner_cycles=1, max_batch=0, rel_tol=1e-10,
                  p_west=None, p_east=None, device=0, w_max_n=64, inner_first=0, separate_coarse=False,
-                 case=2, p_south=None, p_north=None, fuse_cycles=True):
+                 case=2, p_south=None, p_north=None, fuse_cycles=True, cnn_weights=None, warm_min_n=0,
+                 tune_cache=None):
         if case not in BOUNDARY_DEFAULTS:
             raise ValueError("case must be 1 or 2 (Table 1)")
         g = [d if v is None else float(v) for d, v in zip(BOUNDARY_DEFAULTS[case], (p_west, p_east, p_south, p_north))]
@@ -159,7 +171,9 @@ class Context:
         self.hier = Hier(n_levels, n0, 4, 1 if case == 1 else 0, *g)
         self.opts = Opts(SOLVERS[solver], KL_PREC[kl_prec], nu1, nu2, max_cycles, inner_cycles,
                          max_batch, w_max_n, rel_tol, inner_first, 1 if separate_coarse else 0,
-                         1 if fuse_cycles else 0)
+                         1 if fuse_cycles else 0, 1 if cnn_weights is not None else 0, warm_min_n,
+                         None if cnn_weights is None else os.fsencode(cnn_weights),
+                         None if tune_cache is None else os.fsencode(tune_cache))
         self.n_modes = n_modes
         self.n0 = n0
         self.n_levels = n_levels
@@ -338,20 +352,31 @@ def _check_count(rc):
     return rc
 
 
+def _level_dict(o):
+    return dict(n=o.n, mean_y=o.mean_y, var_y=o.var_y, mean_qf=o.mean_qf, var_qf=o.var_qf, mean_qc=o.mean_qc)
+
+
 def estimate(qf_levels, qc_levels, n_shifts=1, stream=None):
-    """MLMC / MLQMC estimate over levels; arrays host or device (float64, 1-D)."""
+    """MLMC / MLQMC estimate over levels; arrays host or device (float64, 1-D).
+    Without a stream (and at most MAX_LEVELS levels) through fmgmc_estimate, the
+    aggregate form; with one through fmgmc_estimate_levels on that stream."""
     L = len(qf_levels)
     n = np.array([int(q.shape[0]) for q in qf_levels], np.int64)
     pf = (C.c_void_p * L)(*[_ptr(q) for q in qf_levels])
     pc = (C.c_void_p * L)(*[_ptr(q) for q in qc_levels])
+    if stream is None and L <= MAX_LEVELS:
+        e = Est()
+        _check(lib().fmgmc_estimate(L, _ptr(n), C.cast(pf, C.c_void_p), C.cast(pc, C.c_void_p), n_shifts,
+                                    C.byref(e)))
+        return dict(levels=[_level_dict(e.level[l]) for l in range(e.n_levels)], mean=e.mean,
+                    var_of_mean=e.var_of_mean)
     out = (LevelEst * L)()
     mean = C.c_double()
     var = C.c_double()
-    _check(lib().fmgmc_estimate(L, _ptr(n), C.cast(pf, C.c_void_p), C.cast(pc, C.c_void_p), n_shifts,
-                                C.cast(out, C.c_void_p), C.byref(mean), C.byref(var), _stream_ptr(stream)))
-    levels = [dict(n=o.n, mean_y=o.mean_y, var_y=o.var_y, mean_qf=o.mean_qf, var_qf=o.var_qf,
-                   mean_qc=o.mean_qc) for o in out]
-    return dict(levels=levels, mean=mean.value, var_of_mean=var.value)
+    _check(lib().fmgmc_estimate_levels(L, _ptr(n), C.cast(pf, C.c_void_p), C.cast(pc, C.c_void_p), n_shifts,
+                                       C.cast(out, C.c_void_p), C.byref(mean), C.byref(var),
+                                       _stream_ptr(stream)))
+    return dict(levels=[_level_dict(o) for o in out], mean=mean.value, var_of_mean=var.value)
 
 
 def header_functions():

@@ -15,6 +15,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as O
 from paper_1910_04727_amd import fmgmc, inputs
+from parity_util import assert_same_solution
 
 pytestmark = pytest.mark.gpu
 
@@ -48,16 +49,6 @@ def run_level(ctx, level, xi):
 def oracle(cfg, n, level, xi, **kw):
     tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
     return O.solve_level(cfg["sigma2"], cfg["corr_len"], tab, n, level, xi, case=1, **kw)
-
-
-def assert_same_solution(g, o, gcyc, ocyc, rel_tol, label):
-    same = np.all(gcyc == ocyc, axis=1)
-    rel = np.abs(g - o) / np.abs(o)
-    log(f"{label}: same cycle counts {same.sum()}/{len(same)}, max rel err (same) "
-        f"{rel[same].max() if same.any() else 0:.2e}, max rel err (all) {rel.max():.2e}")
-    assert same.mean() >= 0.9, (gcyc[~same], ocyc[~same])
-    assert rel[same].max() <= rel_tol
-    assert rel.max() <= 1e-6
 
 
 def test_fp64_all_small_levels_chunked():

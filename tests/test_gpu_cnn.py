@@ -192,7 +192,7 @@ def test_trained_network_saves_cycles_and_keeps_every_q():
             torch.cuda.synchronize()
             out[name] = (rc, qf.cpu().numpy(), qc.cpu().numpy(), cyc.cpu().numpy(), fl.cpu().numpy())
     p, w = out["plain"], out["warm"]
-    rejected = (w[4] & 4) != 0
+    rejected = (w[4] & fmgmc.FLAG_WARM_REJECTED) != 0
     gain = p[3].mean(axis=0) - w[3].mean(axis=0)
     log(f"cycles plain {p[3].mean(axis=0)}, warm {w[3].mean(axis=0)}, saved {gain}, "
         f"warm start rejected for {rejected.sum()} of {S}")

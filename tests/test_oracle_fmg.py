@@ -10,7 +10,13 @@ CFG1 = dict(sigma2=1.0, corr_len=0.3, M=64)
 
 def test_vcycle_factor_below_0p2_cfg1():
     """Residual reduction factor below 0.2 on every cycle of every QoI stage,
-    on the 3-level config (16^2, 32^2, 64^2), down to the round-off floor."""
+    on the 3-level config (16^2, 32^2, 64^2), down to the round-off floor.
+
+    What is pinned here is the oracle's default cycle: V(2,2) red-black Gauss-
+    Seidel on the QoI stage whose coarse-grid corrections on grids n <= 64 are
+    W-cycles (two coarse cycles each), which on these grids makes every
+    correction below the stage a W-cycle. Pure V(2,2) is pinned separately
+    below to a weaker bound: it does not reach 0.2 on every cycle."""
     tab = O.kl_table(CFG1["sigma2"], CFG1["corr_len"], CFG1["M"])
     worst = 0.0
     for lev, n in enumerate([16, 32, 64]):
@@ -24,6 +30,26 @@ def test_vcycle_factor_below_0p2_cfg1():
                 if len(h) > 1:
                     worst = max(worst, float(np.max(h[1:] / h[:-1])))
     assert 0.0 < worst < 0.2, worst
+
+
+def test_pure_v_cycle_factor_cfg1():
+    """Pure V(2,2) (wmax = 0) on the same samples: 90% of the cycles reduce the
+    residual by a factor below 0.2 and every cycle by one below 0.3 (measured:
+    97% below 0.2, median 0.10, worst 0.25)."""
+    tab = O.kl_table(CFG1["sigma2"], CFG1["corr_len"], CFG1["M"])
+    fac = []
+    for lev, n in enumerate([16, 32, 64]):
+        xi = inputs.mc_normals(60, 64, config=1, level=lev)
+        for s in range(xi.shape[0]):
+            K = O.field(n, CFG1["corr_len"], tab, xi[s])
+            out = O.fmg_sample(K, level=lev, tol=1e-13, max_cycles=60, history=True, wmax=0)
+            assert out["flags"] == 0
+            for h in out["hist"]:
+                h = h[h > 1e-13]
+                if len(h) > 1:
+                    fac.extend((h[1:] / h[:-1]).tolist())
+    fac = np.asarray(fac)
+    assert np.quantile(fac, 0.9) < 0.2 and fac.max() < 0.3, (np.quantile(fac, 0.9), fac.max())
 
 
 def test_pure_v_cycle_is_slower_but_converges_to_the_same_q():
