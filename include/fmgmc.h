@@ -264,6 +264,23 @@ int fmgmc_estimate_levels(int32_t n_lev, const int64_t *n, const double *const *
                           double *mean, double *var_of_mean, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * estimate of fmgmc_estimate_levels, bit for bit, with no allocation of any
+ * kind. qf[l] and qc[l] must be device arrays (EINVAL for host arrays, which
+ * would need a staging buffer). Its kernel works in a fixed per-device scratch
+ * array of the library (8 + 4096 doubles, 32.8 KB, held by each device the
+ * library runs on until the process ends), so n_shifts is limited to 4096
+ * (EINVAL above). The scratch keeps the last call's contents; every value is
+ * written before it is read. Calls that overlap on one device (different host
+ * threads or streams) race on that array: serialise them.
+ */
+int fmgmc_estimate_levels_noalloc(int32_t n_lev, const int64_t *n, const double *const *qf,
+                                  const double *const *qc, int32_t n_shifts,
+                                  fmgmc_level_est *levels, double *mean, double *var_of_mean,
+                                  void *stream);
+
+/*
  * Host-only (no device needed): the KL mode table of fmgmc_create for the
  * given field, written to host arrays of n_modes entries (same layout as
  * fmgmc_mode_table). Errors: EINVAL.

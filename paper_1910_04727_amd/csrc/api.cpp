@@ -1425,4 +1425,38 @@ int fmgmc_estimate_levels(int32_t n_lev, const int64_t *n, const double *const *
     return FMGMC_OK;
 }
 
+int fmgmc_estimate_levels_noalloc(int32_t n_lev, const int64_t *n, const double *const *qf,
+                                  const double *const *qc, int32_t n_shifts, fmgmc_level_est *levels,
+                                  double *mean, double *var_of_mean, void *stream) {
+    if (n_lev < 1 || !n || !qf || !qc || n_shifts < 1 || n_shifts > kEstMaxShifts) {
+        set_error("fmgmc_estimate_levels_noalloc: bad arguments (n_shifts must be 1.." +
+                  std::to_string(kEstMaxShifts) + ")");
+        return FMGMC_EINVAL;
+    }
+    for (int l = 0; l < n_lev; ++l) {
+        if (n[l] < 1 || !qf[l] || !qc[l] || (n_shifts > 1 && (n[l] % n_shifts) != 0)) {
+            set_error("fmgmc_estimate_levels_noalloc: bad level sizes");
+            return FMGMC_EINVAL;
+        }
+        if (!is_device_ptr(qf[l]) || !is_device_ptr(qc[l])) {
+            set_error("fmgmc_estimate_levels_noalloc: qf and qc must be device arrays (host arrays would need "
+                      "a staging allocation)");
+            return FMGMC_EINVAL;
+        }
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double *scr = nullptr;
+    TRY(estimate_scratch(&scr));
+    EstAcc acc;
+    for (int l = 0; l < n_lev; ++l) {
+        TRY(launch_level_reduce(qf[l], qc[l], n[l], n_shifts, scr, scr + kEstShiftOffset, st));
+        double h[5] = {0, 0, 0, 0, 0};
+        FMGMC_HIP(hipMemcpyAsync(h, scr, sizeof(h), hipMemcpyDeviceToHost, st));
+        FMGMC_HIP(hipStreamSynchronize(st));
+        acc.add(l, n[l], n_shifts, h, levels);
+    }
+    acc.finish(mean, var_of_mean);
+    return FMGMC_OK;
+}
+
 }  // extern "C"

@@ -184,7 +184,13 @@ int launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
 // estimators: compensated sums in a fixed order
 int launch_level_reduce(const double *qf, const double *qc, int64_t n, int nshift, double *out,
                         double *shift_means, hipStream_t st);
-// largest number of RQMC shifts the estimator reduction takes
+// Allocation-free estimator: the per-device address of the library's fixed
+// scratch array (kEstScratchDoubles doubles: 5 results at 0, per-shift means
+// from kEstShiftOffset, at most kEstMaxShifts of them), looked up on first use.
 constexpr int kEstMaxShifts = 4096;
+constexpr int kEstShiftOffset = 8;
+constexpr int kEstScratchDoubles = kEstShiftOffset + kEstMaxShifts;
+constexpr int kMaxDevices = 64;
+int estimate_scratch(double **out);
 
 }  // namespace fmgmc

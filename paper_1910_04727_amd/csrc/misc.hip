@@ -2,6 +2,7 @@
 // FP64, right-hand-side norms, per-sample convergence bookkeeping and the
 // compensated estimator reductions (Section 2.1 Eqs. (3)-(5), Section 2.4).
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -388,5 +389,39 @@ int launch_level_reduce(const double *qf, const double *qc, int64_t n, int nshif
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
+
+// Fixed device scratch of the allocation-free estimator entry point: slots
+// 0..4 take a level's results, slots 8.. the per-shift means of RQMC. Each
+// device holds its own copy until the process ends; its address is looked
+// up once per device (with that device current) and kept, and host code
+// only ever passes that address on.
+__device__ __align__(256) double scratch[kEstScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int estimate_scratch(double **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        set_error("estimate scratch: no current HIP device (or device index above the library's limit)");
+        return FMGMC_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return FMGMC_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return FMGMC_OK;
+}
 
 }  // namespace fmgmc

@@ -77,6 +77,7 @@ _SIGS = {
     "fmgmc_solve_level": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fmgmc_estimate": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, C.POINTER(Est)]),
     "fmgmc_estimate_levels": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "fmgmc_estimate_levels_noalloc": (C.c_int, [C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "fmgmc_solve_levels": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fmgmc_autotune": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP]),
     "fmgmc_set_schedule": (C.c_int, [_VP, C.c_int32, _VP]),
@@ -376,6 +377,22 @@ def estimate(qf_levels, qc_levels, n_shifts=1, stream=None):
     _check(lib().fmgmc_estimate_levels(L, _ptr(n), C.cast(pf, C.c_void_p), C.cast(pc, C.c_void_p), n_shifts,
                                        C.cast(out, C.c_void_p), C.byref(mean), C.byref(var),
                                        _stream_ptr(stream)))
+    return dict(levels=[_level_dict(o) for o in out], mean=mean.value, var_of_mean=var.value)
+
+
+def estimate_noalloc(qf_levels, qc_levels, n_shifts=1, stream=None):
+    """The estimate of estimate(), through the entry point that allocates nothing
+    (device arrays only; n_shifts <= 4096)."""
+    L = len(qf_levels)
+    n = np.array([int(q.shape[0]) for q in qf_levels], np.int64)
+    pf = (C.c_void_p * L)(*[_ptr(q) for q in qf_levels])
+    pc = (C.c_void_p * L)(*[_ptr(q) for q in qc_levels])
+    out = (LevelEst * L)()
+    mean = C.c_double()
+    var = C.c_double()
+    _check(lib().fmgmc_estimate_levels_noalloc(L, _ptr(n), C.cast(pf, C.c_void_p), C.cast(pc, C.c_void_p),
+                                               n_shifts, C.cast(out, C.c_void_p), C.byref(mean), C.byref(var),
+                                               _stream_ptr(stream)))
     return dict(levels=[_level_dict(o) for o in out], mean=mean.value, var_of_mean=var.value)
 
 
