@@ -62,7 +62,7 @@ def run_form(torch, fmgmc, xi_dev, form, args, tol=None, steps=None, warmup=None
     net = None
     if form == "nn_warm":
         net = fmgmc.Cnn(path=WEIGHTS)
-        ctx.set_warm_start(net, min_n=256)
+        ctx.set_warm_start(net, min_n=args.warm_min_n)
 
     def step():
         rc = ctx.solve_level(LEVEL, xi_dev, qf, qc, cyc, fl)
@@ -181,6 +181,199 @@ def qoi_err(form, ref):
     return {"samples": int(k), "qf_max": float(ef.max()), "qf_median": float(np.median(ef)),
             "qc_max": float(ec.max()), "qc_median": float(np.median(ec)),
             "same_cycles": int(np.all(form["cycles"][:k] == ocyc, axis=1).sum())}
+
+
+# ------------------------------------------------ driver-visible workloads
+# Bounded versions of the report workloads (cfg1..cfg5), run by the default
+# benchmark after the headline so that every configuration is measured in the
+# same run. Each entry states what was reduced relative to the full workload.
+
+def _kl_mfma(prof, dtype):
+    ms, n, flops = prof["kl"]
+    if not n or ms <= 0:
+        return None
+    peak = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}[dtype]
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"tflops": round(tf, 2), "peak_tflops": peak, "frac": round(tf / peak, 4), "ms": round(ms, 3)}
+
+
+def compact_reports(torch, fmgmc, inputs, args):
+    from oracle import oracle as O
+    out = {}
+    t_all = time.perf_counter()
+    # d1: cfg1 in full, FP64, every sample against the oracle
+    cfg = dict(sigma2=1.0, corr_len=0.3, n_modes=64, n_levels=3, n0=16)
+    ns = [1000, 1000, 1000]
+    xis = [inputs.mc_normals(n, cfg["n_modes"], config=1, level=l) for l, n in enumerate(ns)]
+    xd = [_dev(torch, x) for x in xis]
+    res = [_bufs(torch, n) for n in ns]
+    with fmgmc.Context(**cfg, solver="fp64") as ctx:
+        ctx.solve_levels(xd, [o[0] for o in res], [o[1] for o in res])
+        t0 = _t(torch)
+        rc = ctx.solve_levels(xd, *[[o[k] for o in res] for k in range(4)])
+        dt = _t(torch) - t0
+    tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
+    ef, ec, same = [], [], 0
+    for l in range(3):
+        of, oc, ocy, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], tab, cfg["n0"] << l, l, xis[l],
+                                       nthreads=O.max_threads())
+        ef.append(np.abs(res[l][0].cpu().numpy() - of) / np.abs(of))
+        if l:
+            ec.append(np.abs(res[l][1].cpu().numpy() - oc) / np.abs(oc))
+        same += int(np.all(res[l][2].cpu().numpy() == ocy, axis=1).sum())
+    est = fmgmc.estimate([o[0] for o in res], [o[1] for o in res])
+    out["d1_cfg1"] = {"samples_per_s": round(sum(ns) / dt, 1), "status": int(rc),
+                      "qf_max_rel_err_vs_oracle": float(np.concatenate(ef).max()),
+                      "qc_max_rel_err_vs_oracle": float(np.concatenate(ec).max()),
+                      "same_cycles_as_oracle": f"{same}/{sum(ns)}", "estimate": est["mean"],
+                      "workload": "3 levels 16^2/32^2/64^2, 1000 samples each, FP64, rel-res 1e-10 (full size)"}
+    log("reports: d1 done")
+    # d2: cfg2 with the frozen N_l scaled by 1/report_div, both forms
+    cfg = dict(CFG)
+    div = args.report_div
+    ns = [max(16, n // div) for n in _cfg2_counts()]
+    xd = [_dev(torch, inputs.mc_normals_blocked(0, n, cfg["n_modes"], config=2, level=l)) for l, n in enumerate(ns)]
+    d2 = {"n_l": ns, "workload": f"5 levels 32^2..512^2, the frozen N_l divided by {div}, rel-res 1e-10"}
+    Q = {}
+    for f in ("fp32_ir", "fp64"):
+        res = [_bufs(torch, n) for n in ns]
+        with fmgmc.Context(**cfg, solver=f, max_batch=2048, max_cycles=60, w_max_n=args.wmax,
+                           **(dict(inner_first=args.inner_first) if f == "fp32_ir" else {})) as ctx:
+            ctx.solve_levels(xd, [o[0] for o in res], [o[1] for o in res])
+            t0 = _t(torch)
+            rc = ctx.solve_levels(xd, *[[o[k] for o in res] for k in range(4)])
+            dt = _t(torch) - t0
+        est = fmgmc.estimate([o[0] for o in res], [o[1] for o in res])
+        Q[f] = [(o[0].cpu().numpy(), o[1].cpu().numpy()) for o in res]
+        d2[f] = {"samples_per_s": round(sum(ns) / dt, 1), "status": int(rc), "estimate": est["mean"],
+                 "var_of_mean": est["var_of_mean"], "sampling_rmse": float(np.sqrt(est["var_of_mean"])),
+                 "flagged": int(sum(int((o[3] != 0).sum().item()) for o in res))}
+    err = {f: [] for f in Q}
+    for l in range(len(ns)):
+        k = min(8, ns[l])
+        xo = xd[l][:k].cpu().numpy()
+        of, oc = _oracle_subset(cfg, l, xo, 1e-12)
+        for f in Q:
+            err[f].append(np.abs(Q[f][l][0][:k] - of) / np.abs(of))
+            if l:
+                err[f].append(np.abs(Q[f][l][1][:k] - oc) / np.abs(oc))
+    for f in Q:
+        e = np.concatenate(err[f])
+        d2[f]["qoi_rel_err_vs_oracle_at_1e-12"] = {"max": float(e.max()), "median": float(np.median(e)),
+                                                   "values": int(e.size)}
+    d2["estimate_rel_diff_fp32_ir_vs_fp64"] = abs(d2["fp32_ir"]["estimate"] - d2["fp64"]["estimate"]) / abs(
+        d2["fp64"]["estimate"])
+    out["d2_cfg2"] = d2
+    del xd
+    log("reports: d2 done")
+    # d3: cfg3 reduced to 2^m Sobol' points x 16 shifts per level against as many MC samples;
+    # KL contraction in FP64 / FP32 / BF16 on the Sobol' points, with its matrix-core rate
+    cfg = dict(sigma2=2.0, corr_len=0.1, n_modes=512, n_levels=4, n0=64)
+    m_log2, R = args.report_qmc_log2, 16
+    Np = R << m_log2
+    d3 = {"workload": f"4 levels 64^2..512^2, 2^{m_log2} Sobol' points x {R} digital shifts per level against "
+                      f"{Np} i.i.d. samples per level (equal cost), FP32+IR to 1e-10", "levels": []}
+    tot = {"var_rqmc": 0.0, "var_mc": 0.0}
+    prec = {"kl_fp64": "fp64", "kl_fp32": "fp32", "kl_bf16": "bf16"}
+    ctxs = {k: fmgmc.Context(**cfg, solver="fp32_ir", kl_prec=p, max_batch=2048, max_cycles=60,
+                             w_max_n=args.wmax, inner_first=args.inner_first) for k, p in prec.items()}
+    kl_rate = {}
+    for l in range(cfg["n_levels"]):
+        xq = _dev(torch, inputs.rqmc_normals(cfg["n_modes"], m_log2, R, config=3, level=l))
+        row = {"n": cfg["n0"] << l}
+        q = {}
+        for k, ctx in ctxs.items():
+            qf, qc, c, fl = _bufs(torch, Np)
+            ctx.profile(l == cfg["n_levels"] - 1)
+            ctx.solve_level(l, xq, qf, qc, c, fl)
+            ctx.profile(False)
+            pr = ctx.profile_read()
+            if l == cfg["n_levels"] - 1:
+                kl_rate[k] = _kl_mfma(pr, prec[k])
+            q[k] = torch.cat([qf, qc]).cpu().numpy()
+            if k == "kl_fp64":
+                e = fmgmc.estimate([qf], [qc], n_shifts=R)
+                row["rqmc_var_of_mean"] = e["var_of_mean"]
+                tot["var_rqmc"] += e["var_of_mean"]
+        for k in ("kl_fp32", "kl_bf16"):
+            m = q["kl_fp64"] != 0
+            row[f"{k}_qoi_rel_err"] = _rel(q[k][m], q["kl_fp64"][m])
+        xm = _dev(torch, inputs.mc_normals_blocked(0, Np, cfg["n_modes"], config=3, level=l))
+        qf, qc, c, fl = _bufs(torch, Np)
+        ctxs["kl_fp64"].solve_level(l, xm, qf, qc, c, fl)
+        e = fmgmc.estimate([qf], [qc])
+        row["mc_var_of_mean"] = e["var_of_mean"]
+        row["variance_ratio_mc_over_rqmc"] = e["var_of_mean"] / row["rqmc_var_of_mean"]
+        tot["var_mc"] += e["var_of_mean"]
+        d3["levels"].append(row)
+        del xq, xm
+    for c in ctxs.values():
+        c.close()
+    d3["variance_ratio_mc_over_rqmc_total"] = tot["var_mc"] / tot["var_rqmc"]
+    d3["kl_contraction_at_512"] = {
+        "note": "KL synthesis rate on the 512^2 level (FP64: the separable factorisation; FP32 / BF16: the dense "
+                "samples x 512 modes x cells contraction with FP32 accumulation), flops of the path taken over "
+                "the kernel's event-timed duration, against the dense matrix-core peak of its input type",
+        **{k: v for k, v in kl_rate.items()}}
+    out["d3_cfg3"] = d3
+    log("reports: d3 done")
+    # d4: cfg4 in full, all levels in one call
+    cfg = dict(sigma2=3.0, corr_len=0.05, n_modes=1024, n_levels=6, n0=32)
+    ns = [42451, 15007, 5306, 1875, 663, 234]
+    xd = [_dev(torch, inputs.mc_normals_blocked(0, n, cfg["n_modes"], config=4, level=l)) for l, n in enumerate(ns)]
+    res = [_bufs(torch, n) for n in ns]
+    with fmgmc.Context(**cfg, solver="fp32_ir", max_batch=512, max_cycles=60) as ctx:
+        ctx.solve_levels(xd, [o[0] for o in res], [o[1] for o in res])
+        t0 = _t(torch)
+        rc = ctx.solve_levels(xd, *[[o[k] for o in res] for k in range(4)])
+        dt = _t(torch) - t0
+    k = 4
+    of, oc = _oracle_subset(cfg, 5, xd[5][:k].cpu().numpy(), 1e-10)
+    est = fmgmc.estimate([o[0] for o in res], [o[1] for o in res])
+    out["d4_cfg4"] = {"samples_per_s": round(sum(ns) / dt, 1), "status": int(rc),
+                      "flagged": int(sum(int((o[3] != 0).sum().item()) for o in res)),
+                      "cycles_mean_per_level": [[round(float(x), 3) for x in o[2].double().mean(0).cpu().numpy()]
+                                                for o in res],
+                      "qf_1024_rel_err_vs_oracle": _rel(res[5][0][:k].cpu().numpy(), of),
+                      "qc_1024_rel_err_vs_oracle": _rel(res[5][1][:k].cpu().numpy(), oc),
+                      "estimate": est["mean"], "var_of_mean": est["var_of_mean"],
+                      "workload": f"6 levels 32^2..1024^2, sigma2=3, corr_len=0.05, 1024 modes, N_l = {ns} "
+                                  "(65536, full size), FP32+IR to 1e-10, all levels in one solve_levels call"}
+    del xd
+    log("reports: d4 done")
+    # d5: the committed network on 1024 unseen samples at 512^2 against the plain start
+    cfg = dict(CFG)
+    xi_te = _dev(torch, inputs.mc_normals(1024, cfg["n_modes"], config=5, level=LEVEL,
+                                          purpose=inputs.PURPOSE_CNN_TEST))
+    S = xi_te.shape[0]
+    outs = {}
+    with fmgmc.Context(**cfg, solver="fp32_ir", max_batch=S, max_cycles=60, w_max_n=args.wmax,
+                       inner_first=args.inner_first) as ctx, fmgmc.Cnn(path=WEIGHTS) as net:
+        for name, cnn, mn in (("plain", None, 256), ("warm_256", net, 256), ("warm_512", net, 512)):
+            ctx.set_warm_start(cnn, min_n=mn)
+            qf, qc, cyc, fl = _bufs(torch, S)
+            ctx.solve_level(LEVEL, xi_te, qf, qc, cyc, fl)
+            t0 = _t(torch)
+            for _ in range(3):
+                ctx.solve_level(LEVEL, xi_te, qf, qc, cyc, fl)
+            dt = (_t(torch) - t0) / 3
+            outs[name] = (qf.cpu().numpy(), qc.cpu().numpy(), cyc.cpu().numpy(), fl.cpu().numpy(), dt)
+    p = outs["plain"]
+    ep = fmgmc.estimate([p[0]], [p[1]])["mean"]
+    d5 = {"cycles_plain": [round(float(x), 4) for x in p[2].mean(0)], "samples_per_s_plain": round(S / p[4], 1),
+          "workload": "1024 unseen samples (test stream) at 512^2 / 256^2 of the 5-level config, the committed "
+                      "network on the QoI stages n >= min_n (256: both, 512: the fine stage only), FP32+IR to 1e-10"}
+    for name in ("warm_256", "warm_512"):
+        w = outs[name]
+        ew = fmgmc.estimate([w[0]], [w[1]])["mean"]
+        d5[name] = {"cycles_warm": [round(float(x), 4) for x in w[2].mean(0)],
+                    "cycles_saved": [round(float(x), 4) for x in p[2].mean(0) - w[2].mean(0)],
+                    "warm_rejected": int(((w[3] & fmgmc.FLAG_WARM_REJECTED) != 0).sum()),
+                    "samples_per_s_warm": round(S / w[4], 1), "estimate_rel_diff": abs(ew - ep) / abs(ep)}
+    out["d5_cfg5"] = d5
+    log("reports: d5 done")
+    out["seconds"] = round(time.perf_counter() - t_all, 1)
+    return out
 
 
 # ----------------------------------------------------------------- reports
@@ -683,6 +876,11 @@ def main():
     ap.add_argument("--acc-steps", type=int, default=4, help="timed steps per form of the accuracy record")
     ap.add_argument("--saving-steps", type=int, default=3,
                     help="timed steps of the standard-MLMC comparator (0 = skip)")
+    ap.add_argument("--reports", type=int, default=1,
+                    help="1: after the headline, bounded runs of every workload (cfg1..cfg5) in the same line")
+    ap.add_argument("--report-div", type=int, default=16, help="cfg2 in the line: frozen N_l divided by this")
+    ap.add_argument("--report-qmc-log2", type=int, default=10, help="cfg3 in the line: 2^m Sobol' points per shift")
+    ap.add_argument("--warm-min-n", type=int, default=256, help="smallest QoI stage the network starts")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -803,6 +1001,8 @@ def main():
                            "different iterate of the same discrete problem), so the 1e-8 bar is shown with both "
                            "sides driven to this tolerance")
             out["accuracy_at_tight_tol"] = rec
+    if args.reports:
+        out["reports"] = compact_reports(torch, fmgmc, inputs, args)
     print(json.dumps(out), flush=True)
 
 
