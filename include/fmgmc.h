@@ -193,12 +193,15 @@ int fmgmc_solve_level(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, const do
  * with dN_l > 0): level l solves n_samples[l] samples with xi[l]
  * ([n_samples[l]][n_modes]) into q_fine[l], q_coarse[l] (and cycles[l],
  * flags[l] if those tables and entries are non-NULL), as fmgmc_solve_level
- * would. The levels run concurrently, each on its own stream and device
- * workspace (allocated on first use: the finest-level workspace's memory
- * budget per level), so small grids overlap the large ones. Results are
- * identical to per-level fmgmc_solve_level calls. `stream` is synchronised
- * first (inputs may be produced on it); the call returns when every level is
- * done. Returns as fmgmc_solve_level, over all levels.
+ * would. Each level has its own device workspace (allocated on first use:
+ * the finest-level workspace's memory budget per level). The levels run on up
+ * to four concurrent lanes (a host thread and a stream each, so that each lane
+ * keeps a hardware queue of its own), assigned longest first to the least
+ * loaded lane; the levels of one lane run one after another. Small grids thus
+ * overlap the large ones. Results are identical to per-level
+ * fmgmc_solve_level calls. `stream` is synchronised first (inputs may be
+ * produced on it); the call returns when every level is done. Returns as
+ * fmgmc_solve_level, over all levels.
  */
 int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples,
                        const double *const *xi, double *const *q_fine,
@@ -221,6 +224,8 @@ int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples,
 int fmgmc_autotune(fmgmc_ctx *ctx, int32_t level, int64_t n_pilot, const double *xi,
                    int32_t *params);
 int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params);
+/* The level's current schedule (3 entries, as above). */
+int fmgmc_get_schedule(const fmgmc_ctx *ctx, int32_t level, int32_t *params);
 
 /* Per-level statistics of the estimators. */
 typedef struct {

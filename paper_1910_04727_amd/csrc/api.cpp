@@ -49,6 +49,7 @@ namespace {
 
 constexpr int kMaxGrid = 9;    // grid indices: n_coarsest << k
 constexpr int kSmallTop = 32;  // grids up to this size run whole cycles in LDS
+constexpr int kMaxLanes = 4;   // concurrent levels in fmgmc_solve_levels (one hardware queue each)
 
 int ilog2(int v) {
     int r = 0;
@@ -117,7 +118,8 @@ struct Work {
     double *rr = nullptr, *q = nullptr, *bnorm = nullptr, *qf = nullptr, *qc = nullptr, *xi = nullptr;
     int32_t *active = nullptr, *cycles = nullptr, *n_active = nullptr;
     uint8_t *flags = nullptr;
-    int32_t *h_n_active = nullptr;  // pinned
+    int32_t *h_n_active = nullptr;  // pinned, 2 slots (cycle blocks in flight)
+    hipEvent_t blk_ev[2] = {};      // the copy of each in-flight block's active count
     int n_active_host = 0;
     int top_grid = -1;
     bool profile = false;           // profiling records allowed for this workspace
@@ -156,6 +158,10 @@ void free_work(Work &w) {
     w.p0_cap = 0;
     if (w.h_n_active) (void)hipHostFree(w.h_n_active);
     w.h_n_active = nullptr;
+    for (auto &e : w.blk_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     for (auto &kv : w.graphs) (void)hipGraphExecDestroy(kv.second);
     w.graphs.clear();
     if (w.own_stream) (void)hipStreamDestroy(w.own_stream);
@@ -180,6 +186,7 @@ struct fmgmc_ctx {
     double *d_sqrtlam = nullptr;
     Work main;                                  // finest-level workspace (fmgmc_solve_level)
     std::vector<std::unique_ptr<Work>> lev;     // per-level workspaces (fmgmc_solve_levels)
+    std::vector<hipStream_t> lanes;             // fmgmc_solve_levels: one stream per host thread
     std::vector<Tune> tune;                     // per MLMC level
     const fmgmc_cnn *warm = nullptr;            // learned warm start
     int warm_min_n = 256;
@@ -255,10 +262,11 @@ int alloc_work(const fmgmc_ctx *c, Work &w, int S, int n_top) {
     TRY(dalloc(&w.active, S)); TRY(dalloc(&w.cycles, 2 * size_t(S))); TRY(dalloc(&w.n_active, 1));
     TRY(dalloc(&w.flags, S));
     TRY(dalloc(&w.rr0, S));
-    if (hipHostMalloc(reinterpret_cast<void **>(&w.h_n_active), sizeof(int32_t)) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&w.h_n_active), 2 * sizeof(int32_t)) != hipSuccess) {
         set_error("hipHostMalloc failed");
         return FMGMC_ENOMEM;
     }
+    for (auto &e : w.blk_ev) FMGMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return FMGMC_OK;
 }
 
@@ -298,6 +306,9 @@ void free_ctx(fmgmc_ctx *c) {
     for (auto &w : c->lev)
         if (w) free_work(*w);
     c->lev.clear();
+    for (auto &st : c->lanes)
+        if (st) (void)hipStreamDestroy(st);
+    c->lanes.clear();
 }
 
 // ------------------------------------------------------------ measurement
@@ -495,21 +506,51 @@ int prepare(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int level, int t, hipStream
 }
 
 // Cycles of one QoI stage after its first step (first_done cycles): blocks of G
-// steps of per_cycle cycles (+ check) with one host read per block, until no
-// sample is left or max_cycles is reached.
+// steps of per_cycle cycles (+ check), until no sample is left or max_cycles is
+// reached. Each block ends with an asynchronous copy of the number of samples
+// still iterating, and the next block is enqueued before that count reaches the
+// host, so the device never waits for the host between blocks. A block
+// enqueued after every sample has converged is a set of empty launches (each
+// kernel returns at once for an inactive sample), so the results are those of
+// one block at a time. With profiling on, blocks run one at a time: the
+// recorded traffic counts the samples active at each launch.
 int iterate_stage(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int k, int S, int first_done, int per_cycle,
                   int na, hipStream_t st, const std::function<int()> &cycle_and_check) {
     const int G = std::max(1, tn.check_every);
-    int done = first_done;
-    while (na > 0 && done < c->opts.max_cycles) {
-        const int g = std::min(G, (c->opts.max_cycles - done + per_cycle - 1) / per_cycle);
-        const bool graph = tn.graphs && !(c->prof && W.profile);
-        TRY(run_block(W, graph, std::make_tuple(level, k, g, S), st, [&]() -> int {
-            for (int i = 0; i < g; ++i) TRY(cycle_and_check());
-            return FMGMC_OK;
-        }));
-        TRY(read_active(W, st, &na));
-        done += g * per_cycle;
+    const bool prof = c->prof && W.profile;
+    const int ahead = prof ? 1 : 2;  // blocks whose count the host has not read yet
+    int done = first_done, inflight = 0, next = 0;
+    int slots[2] = {0, 0};
+    if (na < 0) {  // the first step's count is not read yet: it is the first block in flight
+        FMGMC_HIP(hipMemcpyAsync(W.h_n_active, W.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FMGMC_HIP(hipEventRecord(W.blk_ev[0], st));
+        slots[inflight++] = 0;
+        next = 1;
+        na = 1;
+    }
+    while (true) {
+        if (na > 0 && done < c->opts.max_cycles && inflight < ahead) {
+            const int g = std::min(G, (c->opts.max_cycles - done + per_cycle - 1) / per_cycle);
+            const bool graph = tn.graphs && !prof;
+            TRY(run_block(W, graph, std::make_tuple(level, k, g, S), st, [&]() -> int {
+                for (int i = 0; i < g; ++i) TRY(cycle_and_check());
+                return FMGMC_OK;
+            }));
+            const int slot = next;
+            next ^= 1;
+            FMGMC_HIP(hipMemcpyAsync(W.h_n_active + slot, W.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            FMGMC_HIP(hipEventRecord(W.blk_ev[slot], st));
+            slots[inflight++] = slot;
+            done += g * per_cycle;
+            continue;
+        }
+        if (inflight == 0) break;
+        const int slot = slots[0];
+        FMGMC_HIP(hipEventSynchronize(W.blk_ev[slot]));
+        na = W.h_n_active[slot];
+        W.n_active_host = na;
+        slots[0] = slots[1];
+        --inflight;
     }
     return FMGMC_OK;
 }
@@ -557,8 +598,7 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
             }
             TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st));
             TRY(launch_checks(c, W, S, slot, qout, 1, tol, st));
-            TRY(read_active(W, st, &na));
-            TRY(iterate_stage(c, W, tn, level, k, S, 1, 1, na, st, [&]() -> int {
+            TRY(iterate_stage(c, W, tn, level, k, S, 1, 1, -1, st, [&]() -> int {
                 TRY(vcycle<double>(c, W, B, S, k, q, INIT_LOAD, false, OUT_RR | OUT_Q, st));
                 return launch_checks(c, W, S, slot, qout, 1, tol, st);
             }));
@@ -677,10 +717,8 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
                 else TRY(launch_ir(iu, S, st));
                 return launch_checks(c, W, S, slot, qout, ni, tol, st);
             };
-            int na;
             TRY(step(first));
-            TRY(read_active(W, st, &na));
-            TRY(iterate_stage(c, W, tn, level, k, S, first, inner, na, st, [&] { return step(inner); }));
+            TRY(iterate_stage(c, W, tn, level, k, S, first, inner, -1, st, [&] { return step(inner); }));
             if (capt) TRY(launch_pack_t(n, S, W.p64[k], W.p0, W.rr0, capt, st));
         }
         return FMGMC_OK;
@@ -1164,21 +1202,52 @@ int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples, 
     std::vector<int> rcs(n_lev, FMGMC_OK);
     std::vector<std::string> msgs(n_lev);
     std::vector<char> ncs(n_lev, 0), nfs(n_lev, 0);
-    auto run = [&](int l) {
-        (void)hipSetDevice(ctx->device);
-        bool nc = false, nf = false;
-        rcs[l] = solve_level_on(ctx, *ws[l], ctx->tune[l], l, n_samples[l], xi[l], q_fine[l], q_coarse[l],
-                                cycles ? cycles[l] : nullptr, flags ? flags[l] : nullptr, ws[l]->own_stream, &nc,
-                                &nf);
-        if (rcs[l] != FMGMC_OK) msgs[l] = g_err;
-        ncs[l] = nc;
-        nfs[l] = nf;
+    // Lanes: at most kMaxLanes host threads, each with one stream, so that every
+    // lane keeps a hardware queue of its own (the runtime maps streams onto a
+    // few hardware queues; two levels sharing one would interleave their many
+    // launches in order). Levels go to lanes longest first, each to the lane
+    // with the least estimated work (samples x cells, with a floor on the cells
+    // for the per-sample cost of the small grids); a lane runs its levels one
+    // after another, the first lane on the calling thread.
+    std::vector<int> order;
+    for (int l = 0; l < n_lev; ++l)
+        if (n_samples[l] > 0) order.push_back(l);
+    auto cost = [&](int l) {
+        const double n = double(ctx->hier.n0 << l);
+        return double(n_samples[l]) * std::max(n * n, 4096.0);
     };
-    // the finest level on the calling thread, every other level on a thread of its own
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    const int nl = std::min<int>(int(order.size()), kMaxLanes);
+    while (int(ctx->lanes.size()) < nl) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            set_error("fmgmc_solve_levels: hipStreamCreate failed");
+            return FMGMC_EHIP;
+        }
+        ctx->lanes.push_back(st);
+    }
+    std::vector<std::vector<int>> lane_levels(nl);
+    std::vector<double> load(nl, 0.0);
+    for (int l : order) {
+        const int j = int(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_levels[j].push_back(l);
+        load[j] += cost(l);
+    }
+    auto run_lane = [&](int j) {
+        for (int l : lane_levels[j]) {
+            (void)hipSetDevice(ctx->device);
+            bool nc = false, nf = false;
+            rcs[l] = solve_level_on(ctx, *ws[l], ctx->tune[l], l, n_samples[l], xi[l], q_fine[l], q_coarse[l],
+                                    cycles ? cycles[l] : nullptr, flags ? flags[l] : nullptr, ctx->lanes[j], &nc,
+                                    &nf);
+            if (rcs[l] != FMGMC_OK) msgs[l] = g_err;
+            ncs[l] = nc;
+            nfs[l] = nf;
+        }
+    };
     std::vector<std::thread> th;
-    for (int l = 0; l < n_lev - 1; ++l)
-        if (n_samples[l] > 0) th.emplace_back(run, l);
-    if (n_samples[n_lev - 1] > 0) run(n_lev - 1);
+    for (int j = 1; j < nl; ++j) th.emplace_back(run_lane, j);
+    if (nl > 0) run_lane(0);
     for (auto &t : th) t.join();
     bool nc = false, nf = false;
     for (int l = 0; l < n_lev; ++l) {
@@ -1262,6 +1331,17 @@ int fmgmc_set_schedule(fmgmc_ctx *ctx, int32_t level, const int32_t *params) {
     ctx->tune[level].check_every = params[0];
     ctx->tune[level].graphs = params[1];
     ctx->tune[level].batch = params[2];
+    return FMGMC_OK;
+}
+
+int fmgmc_get_schedule(const fmgmc_ctx *ctx, int32_t level, int32_t *params) {
+    if (!ctx || level < 0 || level >= ctx->hier.n_levels || !params) {
+        set_error("fmgmc_get_schedule: bad arguments");
+        return FMGMC_EINVAL;
+    }
+    params[0] = ctx->tune[level].check_every;
+    params[1] = ctx->tune[level].graphs;
+    params[2] = ctx->tune[level].batch;
     return FMGMC_OK;
 }
 

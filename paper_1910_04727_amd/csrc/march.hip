@@ -93,8 +93,12 @@ constexpr int march_ring_rows(int nh) { return nh + 3 <= 8 ? 8 : 16; }
 
 template <typename T, int NH, bool CK, int INIT, bool RHSA, int OUT>
 __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
-    constexpr int U = NH + 1;    // register ring depth = prefetch distance = unroll
+    constexpr int U = NH + 1;    // register ring depth = unroll
     constexpr int RX = march_ring_rows(NH);  // LDS x ring rows (>= NH + 3), power of two
+    // prefetch distance of the load queue (a divisor of U, so that a row's queue
+    // slot is a constant after unrolling). Measured: three rows instead of nine
+    // in the eight-half-sweep pass frees 42 VGPRs but runs 2% slower.
+    constexpr int D = U;
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
     constexpr bool LX = (INIT == INIT_LOAD || INIT == INIT_PROLONG);
@@ -120,9 +124,9 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     const T cgS = (INIT == INIT_INTERP) ? gS : T(0), cgN = (INIT == INIT_INTERP) ? gN : T(0);
     const bool first = (l == 0), last = (l == nl - 1);
 
-    // prefetch queue, slot = row % U
-    V2<T> qx[U], qk[U], qb[U], qf[U];
-    T qc[U], qe[U];
+    // prefetch queue, slot = row % D
+    V2<T> qx[D], qk[D], qb[D], qf[D];
+    T qc[D], qe[D];
     auto fetch = [&](int slot, int row) {
         const size_t idx = base + size_t(row) * n + 2 * l;
         if (LX) qx[slot] = ld2_nt(A.x + idx);
@@ -140,11 +144,16 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
         }
     };
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < D; ++u)
         if (u < n) fetch(u, u);
 
     // coefficient ring, slot = row % U: faces west of cell 0, between the cells,
-    // east of cell 1; south / north faces and 1/diagonal of both cells; rhs.
+    // east of cell 1; south / north faces and 1/diagonal of both cells; rhs
+    // (RHSA; a boundary-data rhs is formed from the faces where it is used).
+    // SN (FP32): no south-face ring; a row's south faces are read as the north
+    // faces of the row below (the same values). FP64 keeps the ring: without it
+    // the compiler spills its correction passes.
+    constexpr bool SN = sizeof(T) == 4;
     T rw[U], rm[U], re[U], rs0[U], rs1[U], rn0[U], rn1[U], ri0[U], ri1[U], rb0[U], rb1[U];
 #pragma unroll
     for (int k = 0; k < U; ++k)

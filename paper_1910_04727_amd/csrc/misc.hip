@@ -218,25 +218,43 @@ __global__ __launch_bounds__(256) void k_bnorm(int n, const T *K, Bnd g, double 
 __global__ __launch_bounds__(1024) void k_check(CheckArgs A, int S) {
     __shared__ int cnt[16];
     int mine = 0;
-    for (int s = threadIdx.x; s < S; s += blockDim.x) {
-        if (A.active[s] == 0) continue;
-        const int cyc = (A.cycles[2 * s + A.slot] += A.inc);
-        const double rel = sqrt(A.rr[s]) / A.bnorm[s];
-        bool stop = false;
-        if (!isfinite(rel)) {
-            A.flags[s] |= FMGMC_FLAG_NONFINITE;
-            stop = true;
-        } else if (rel <= A.tol) {
-            stop = true;
-        } else if (A.inc > 0 && cyc >= A.max_cycles) {
-            A.flags[s] |= FMGMC_FLAG_NOTCONV;
-            stop = true;
+    // four samples per lane and round, their inputs loaded before any is decided
+    // (the loads of a round overlap; every sample is read and written by one lane)
+    constexpr int R = 4;
+    for (int s0 = threadIdx.x; s0 < S; s0 += R * blockDim.x) {
+        int act[R], cy[R];
+        double rr[R], bn[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int s = s0 + u * int(blockDim.x);
+            act[u] = s < S ? A.active[s] : 0;
+            cy[u] = s < S ? A.cycles[2 * s + A.slot] : 0;
+            rr[u] = s < S ? A.rr[s] : 0.0;
+            bn[u] = s < S ? A.bnorm[s] : 1.0;
         }
-        if (stop) {
-            A.active[s] = 0;
-            A.qout[s] = A.q[s];
-        } else {
-            ++mine;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int s = s0 + u * int(blockDim.x);
+            if (act[u] == 0) continue;
+            const int cyc = cy[u] + A.inc;
+            A.cycles[2 * s + A.slot] = cyc;
+            const double rel = sqrt(rr[u]) / bn[u];
+            bool stop = false;
+            if (!isfinite(rel)) {
+                A.flags[s] |= FMGMC_FLAG_NONFINITE;
+                stop = true;
+            } else if (rel <= A.tol) {
+                stop = true;
+            } else if (A.inc > 0 && cyc >= A.max_cycles) {
+                A.flags[s] |= FMGMC_FLAG_NOTCONV;
+                stop = true;
+            }
+            if (stop) {
+                A.active[s] = 0;
+                A.qout[s] = A.q[s];
+            } else {
+                ++mine;
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);

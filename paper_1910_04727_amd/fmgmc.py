@@ -81,6 +81,7 @@ _SIGS = {
     "fmgmc_solve_levels": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fmgmc_autotune": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP]),
     "fmgmc_set_schedule": (C.c_int, [_VP, C.c_int32, _VP]),
+    "fmgmc_get_schedule": (C.c_int, [_VP, C.c_int32, _VP]),
     "fmgmc_profile_enable": (C.c_int, [_VP, C.c_int32]),
     "fmgmc_profile_read": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
     "fmgmc_cnn_create": (C.c_int, [C.POINTER(_VP), C.c_uint64, C.c_int32]),
@@ -261,6 +262,11 @@ class Context:
     def set_schedule(self, level, check_every=1, graphs=0, batch=0):
         p = np.array([check_every, graphs, batch], np.int32)
         _check(lib().fmgmc_set_schedule(self._h, level, _ptr(p)))
+
+    def schedule(self, level):
+        p = np.zeros(3, np.int32)
+        _check(lib().fmgmc_get_schedule(self._h, level, _ptr(p)))
+        return dict(check_every=int(p[0]), graphs=int(p[1]), batch=int(p[2]))
 
 
     def set_warm_start(self, cnn, min_n=256):

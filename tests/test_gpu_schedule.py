@@ -155,3 +155,43 @@ def test_schedule_argument_errors():
                 ctx.set_schedule(0, *bad)
         with pytest.raises(RuntimeError):
             ctx.set_schedule(3, 1, 0, 0)
+
+
+@pytest.mark.parametrize("solver", ["fp64", "fp32_ir"])
+def test_more_levels_than_lanes(solver):
+    """Six levels (8^2..256^2) on at most four lanes: some lanes run two levels
+    back to back on one stream; every level equals its own solve bit for bit."""
+    cfg = dict(sigma2=1.0, corr_len=0.2, n_modes=64, n_levels=6, n0=8)
+    ns = [29, 17, 11, 7, 5, 3]
+    xis = [torch.from_numpy(inputs.mc_normals(ns[l], cfg["n_modes"], config=2, level=l, purpose=1)).to("cuda")
+           for l in range(6)]
+    log(f"six levels on lanes, {solver}")
+    with fmgmc.Context(**cfg, solver=solver, max_batch=4) as ctx:
+        ref = [solve(ctx, l, xis[l]) for l in range(6)]
+        outs = [bufs(n) for n in ns]
+        rc = ctx.solve_levels(xis, *[[o[k] for o in outs] for k in range(4)])
+        torch.cuda.synchronize()
+    assert rc == 0
+    for l in range(6):
+        assert ref[l][0] == 0
+        same((0,) + tuple(t.cpu().numpy() for t in outs[l]), ref[l], f"level {l}")
+
+
+def test_schedule_file_round_trip(tmp_path):
+    """fmgmc_autotune writes the per-level schedules to the context's schedule file;
+    a new context of the same hierarchy and solver reads them back, one of another
+    solver ignores the file."""
+    path = tmp_path / "schedule.txt"
+    xi = torch.from_numpy(inputs.mc_normals(64, CFG1["n_modes"], config=1, level=2)).to("cuda")
+    with fmgmc.Context(**CFG1, solver="fp32_ir", max_batch=64, tune_cache=path) as ctx:
+        tuned = ctx.autotune(2, xi)
+        ctx.set_schedule(1, check_every=3, graphs=0, batch=0)
+        ctx.autotune(0, xi[:16])   # rewrites the file with every level's schedule
+        want = [ctx.schedule(l) for l in range(3)]
+    assert want[2] == tuned and want[1] == dict(check_every=3, graphs=0, batch=0)
+    text = path.read_text().splitlines()
+    assert text[0].startswith("fmgmc-schedule 1") and len(text) == 4
+    with fmgmc.Context(**CFG1, solver="fp32_ir", max_batch=64, tune_cache=path) as ctx:
+        assert [ctx.schedule(l) for l in range(3)] == want
+    with fmgmc.Context(**CFG1, solver="fp64", max_batch=64, tune_cache=path) as ctx:
+        assert ctx.schedule(1) == dict(check_every=1, graphs=0, batch=0)
