@@ -42,7 +42,8 @@ WEIGHTS = os.path.join(ROOT, "paper_1910_04727_amd", "weights", "cnn_cfg2.bin")
 
 
 def run_form(torch, fmgmc, xi_dev, form, args, tol=None, steps=None, warmup=None, separate_coarse=False):
-    """form: fp32_ir, fp64, or nn_warm (fp32_ir started from the trained network on 256^2 and 512^2).
+    """form: fp32_ir, fp64, or nn_warm (fp32_ir whose QoI stages with warm_min_n <= n <= warm_max_n start
+    from the trained network: by default the 256^2 stage).
     tol / steps / warmup default to the command line's; separate_coarse: the standard-MLMC
     comparator (Q^c from its own FMG solve on 256^2)."""
     tol = args.tol if tol is None else tol
@@ -62,7 +63,7 @@ def run_form(torch, fmgmc, xi_dev, form, args, tol=None, steps=None, warmup=None
     net = None
     if form == "nn_warm":
         net = fmgmc.Cnn(path=WEIGHTS)
-        ctx.set_warm_start(net, min_n=args.warm_min_n)
+        ctx.set_warm_start(net, min_n=args.warm_min_n, max_n=args.warm_max_n)
 
     def step():
         rc = ctx.solve_level(LEVEL, xi_dev, qf, qc, cyc, fl)
@@ -349,8 +350,9 @@ def compact_reports(torch, fmgmc, inputs, args):
     outs = {}
     with fmgmc.Context(**cfg, solver="fp32_ir", max_batch=S, max_cycles=60, w_max_n=args.wmax,
                        inner_first=args.inner_first) as ctx, fmgmc.Cnn(path=WEIGHTS) as net:
-        for name, cnn, mn in (("plain", None, 256), ("warm_256", net, 256), ("warm_512", net, 512)):
-            ctx.set_warm_start(cnn, min_n=mn)
+        for name, cnn, mn, mx in (("plain", None, 256, 0), ("warm_256", net, 256, 256), ("warm_512", net, 512, 0),
+                                  ("warm_both", net, 256, 0)):
+            ctx.set_warm_start(cnn, min_n=mn, max_n=mx)
             qf, qc, cyc, fl = _bufs(torch, S)
             ctx.solve_level(LEVEL, xi_te, qf, qc, cyc, fl)
             t0 = _t(torch)
@@ -362,8 +364,9 @@ def compact_reports(torch, fmgmc, inputs, args):
     ep = fmgmc.estimate([p[0]], [p[1]])["mean"]
     d5 = {"cycles_plain": [round(float(x), 4) for x in p[2].mean(0)], "samples_per_s_plain": round(S / p[4], 1),
           "workload": "1024 unseen samples (test stream) at 512^2 / 256^2 of the 5-level config, the committed "
-                      "network on the QoI stages n >= min_n (256: both, 512: the fine stage only), FP32+IR to 1e-10"}
-    for name in ("warm_256", "warm_512"):
+                      "network on the 256^2 stage only (warm_256), the 512^2 stage only (warm_512) or both "
+                      "(warm_both), FP32+IR to 1e-10"}
+    for name in ("warm_256", "warm_512", "warm_both"):
         w = outs[name]
         ew = fmgmc.estimate([w[0]], [w[1]])["mean"]
         d5[name] = {"cycles_warm": [round(float(x), 4) for x in w[2].mean(0)],
@@ -881,6 +884,9 @@ def main():
     ap.add_argument("--report-div", type=int, default=16, help="cfg2 in the line: frozen N_l divided by this")
     ap.add_argument("--report-qmc-log2", type=int, default=10, help="cfg3 in the line: 2^m Sobol' points per shift")
     ap.add_argument("--warm-min-n", type=int, default=256, help="smallest QoI stage the network starts")
+    ap.add_argument("--warm-max-n", type=int, default=256,
+                    help="largest QoI stage the network starts (0: no bound); on the 512^2 stage the network "
+                         "saves no cycle (the cfg5 report measures both)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -948,6 +954,8 @@ def main():
             "kl_ms_per_step": round(kl_ms / args.steps, 3) if kl_n else None,
         }
         cnn_ms, cnn_n, cnn_flops = f["prof"]["cnn"]
+        if k == "nn_warm":
+            out["forms"][k]["warm_stages_n"] = [args.warm_min_n, args.warm_max_n or N]
         if cnn_n:
             out["forms"][k]["cnn_tflops"] = round(cnn_flops / (cnn_ms * 1e-3) / 1e12, 2)
             out["forms"][k]["cnn_ms_per_step"] = round(cnn_ms / args.steps, 3)

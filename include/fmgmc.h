@@ -127,6 +127,7 @@ typedef struct {
                               every QoI stage with n >= warm_min_n from it (as
                               fmgmc_set_warm_start); needs FMGMC_SOLVER_FP32_IR and Case II */
     int32_t warm_min_n;    /* smallest QoI stage grid the network starts (0 = 256) */
+    int32_t warm_max_n;    /* largest QoI stage grid the network starts (0 = no bound) */
     const char *cnn_weights; /* network file (fmgmc_cnn_save format) for FMGMC_WARM_CNN, else NULL */
     const char *tune_cache;  /* NULL, or a schedule file: fmgmc_create reads the per-level schedules
                                 from it when it exists and was written for the same hierarchy and
@@ -342,7 +343,7 @@ int fmgmc_profile_read(fmgmc_ctx *ctx, int32_t kind, double *ms, int64_t *launch
  * ---------------------------------------------------------------------------
  */
 #define FMGMC_CNN_PARAMS 37889
-enum { FMGMC_CNN_FP32 = 0, FMGMC_CNN_BF16 = 1 };
+enum { FMGMC_CNN_FP32 = 0, FMGMC_CNN_BF16 = 1, FMGMC_CNN_BF16_FUSED = 2 };
 enum { FMGMC_CNN_LOSS_ERROR = 0, FMGMC_CNN_LOSS_RESIDUAL = 1 };
 typedef struct fmgmc_cnn fmgmc_cnn;
 
@@ -359,8 +360,11 @@ int fmgmc_cnn_load(fmgmc_cnn *cnn, const char *path);
 /*
  * Forward pass on device buffers: x [batch][2][n][n] float (channel 0 = log K,
  * channel 1 = the normalised residual), y [batch][n][n] float. n a power of
- * two in [16, 1024]. prec FMGMC_CNN_FP32 (training kernels) or
- * FMGMC_CNN_BF16 (the solver's inference kernels).
+ * two in [16, 1024]. prec FMGMC_CNN_FP32 (training kernels), FMGMC_CNN_BF16
+ * (BF16 matrix-core inference, one launch per layer, activations through
+ * device memory) or FMGMC_CNN_BF16_FUSED (the solver's inference: all layers
+ * in one pass over row strips with the activations on chip; the same results
+ * as FMGMC_CNN_BF16, batch at most 65535).
  */
 int fmgmc_cnn_forward(fmgmc_cnn *cnn, int32_t n, int64_t batch, const float *x, float *y, int32_t prec,
                       void *stream);
@@ -401,6 +405,8 @@ int fmgmc_cnn_train(fmgmc_ctx *ctx, fmgmc_cnn *cnn, int32_t level, int64_t n_sam
  * contexts only (FMGMC_EINVAL otherwise): its residual loss is that operator.
  */
 int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n);
+/* The same for the QoI stages with min_n <= n <= max_n (max_n = 0: no bound). */
+int fmgmc_set_warm_range(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n, int32_t max_n);
 
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *fmgmc_last_error(void);

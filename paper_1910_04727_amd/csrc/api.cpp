@@ -190,6 +190,7 @@ struct fmgmc_ctx {
     std::vector<Tune> tune;                     // per MLMC level
     const fmgmc_cnn *warm = nullptr;            // learned warm start
     int warm_min_n = 256;
+    int warm_max_n = 0;                         // 0: no upper bound
     fmgmc_cnn *owned_warm = nullptr;            // network loaded from opts.cnn_weights (owned)
     std::string tune_path;                      // opts.tune_cache ("" = none)
     // measurement hooks
@@ -614,18 +615,6 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
 template <typename F>
 int warm_start(fmgmc_ctx *c, Work &W, int k, int S, const IRArgs &ia, hipStream_t st, F &&interp) {
     const int n = W.nsz[k];
-    const size_t per = size_t(n) * n * kCnnWidth * 2;
-    const int sub = int(std::max<size_t>(1, std::min<size_t>(size_t(S), (size_t(256) << 20) / per)));
-    if (W.act_cap < sub * per) {
-        FMGMC_HIP(hipStreamSynchronize(st));
-        for (int j = 0; j < 2; ++j) {
-            if (W.act[j]) (void)hipFree(W.act[j]);
-            W.act[j] = nullptr;
-        }
-        W.act_cap = 0;
-        for (int j = 0; j < 2; ++j) TRY(dalloc(reinterpret_cast<char **>(&W.act[j]), sub * per));
-        W.act_cap = sub * per;
-    }
     InferArgs a{};
     a.n = n;
     a.S = S;
@@ -634,14 +623,17 @@ int warm_start(fmgmc_ctx *c, Work &W, int k, int S, const IRArgs &ia, hipStream_
     a.in_stride = int64_t(n) * n;
     a.log0 = 1;
     a.rr = W.rr0;
-    a.p = W.p64[k];
+    a.e = W.x32[k];  // rms(r) y in FP32 (the stage's FP32 iterate is free until its first cycle)
     a.active = W.active;
     // useful flops per cell, 2 per multiply-add: first layer 18 x 32, four residual
     // layers 288 x 32 each, output layer 288
     const double flops = double(W.n_active_host) * n * n * 2.0 * (18.0 * 32 + 4.0 * 288 * 32 + 288);
-    TRY(timed(c, W, FMGMC_PROF_CNN, flops, st,
-              [&] { return launch_cnn_infer(a, cnn_packed(c->warm), W.act[0], W.act[1], sub, st); }));
-    TRY(launch_ir(ia, S, st));
+    // all layers in one pass with the activations on chip
+    TRY(timed(c, W, FMGMC_PROF_CNN, flops, st, [&] { return launch_cnn_fused(a, cnn_packed(c->warm), st); }));
+    // p += rms(r) y in FP64 and the residual of the corrected start, in one refinement pass
+    IRArgs iw = ia;
+    iw.e = W.x32[k];
+    TRY(launch_ir(iw, S, st));
     TRY(launch_judge(S, W.rr, W.rr0, W.active, W.flags, st));  // active <- samples to restore
     TRY(interp());
     TRY(launch_ir(ia, S, st));
@@ -692,7 +684,7 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
                 if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
                 else TRY(launch_ir(ia, S, st));
             }
-            const bool warm = c->warm && n >= c->warm_min_n;
+            const bool warm = c->warm && n >= c->warm_min_n && (c->warm_max_n == 0 || n <= c->warm_max_n);
             float *capx = W.cap_x[slot], *capt = W.cap_t[slot];
             if (warm || capx) TRY(launch_copy_f64(W.rr, W.rr0, S, st));
             if (capx) {
@@ -753,6 +745,7 @@ int validate(const fmgmc_field *f, const fmgmc_hier *h, const fmgmc_opts *o) {
         (o->solver != FMGMC_SOLVER_FP32_IR || h->boundary != FMGMC_BC_MIXED || !o->cnn_weights))
         return FMGMC_EINVAL;
     if (o->warm_min_n != 0 && o->warm_min_n < 16) return FMGMC_EINVAL;
+    if (o->warm_max_n < 0) return FMGMC_EINVAL;
     return FMGMC_OK;
 }
 
@@ -1030,7 +1023,9 @@ int fmgmc_create(fmgmc_ctx **out, const fmgmc_field *field, const fmgmc_hier *hi
     if (rc == FMGMC_OK && opts->warm == FMGMC_WARM_CNN) {
         rc = fmgmc_cnn_create(&c->owned_warm, 0, device);
         if (rc == FMGMC_OK) rc = fmgmc_cnn_load(c->owned_warm, opts->cnn_weights);
-        if (rc == FMGMC_OK) rc = fmgmc_set_warm_start(c.get(), c->owned_warm, opts->warm_min_n > 0 ? opts->warm_min_n : 256);
+        if (rc == FMGMC_OK)
+            rc = fmgmc_set_warm_range(c.get(), c->owned_warm, opts->warm_min_n > 0 ? opts->warm_min_n : 256,
+                                      opts->warm_max_n);
     }
     if (rc != FMGMC_OK) {
         free_ctx(c.get());
@@ -1346,7 +1341,11 @@ int fmgmc_get_schedule(const fmgmc_ctx *ctx, int32_t level, int32_t *params) {
 }
 
 int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n) {
-    if (!ctx || min_n < 16 || (cnn && !ir_mode(ctx)) || (cnn && cnn->device != ctx->device) ||
+    return fmgmc_set_warm_range(ctx, cnn, min_n, 0);
+}
+
+int fmgmc_set_warm_range(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n, int32_t max_n) {
+    if (!ctx || min_n < 16 || max_n < 0 || (cnn && !ir_mode(ctx)) || (cnn && cnn->device != ctx->device) ||
         (cnn && ctx->hier.boundary != FMGMC_BC_MIXED)) {
         set_error("fmgmc_set_warm_start: bad arguments (FP32_IR solver, Case II boundaries, min_n >= 16, same device)");
         return FMGMC_EINVAL;
@@ -1358,6 +1357,7 @@ int fmgmc_set_warm_start(fmgmc_ctx *ctx, const fmgmc_cnn *cnn, int32_t min_n) {
     }
     ctx->warm = cnn;
     ctx->warm_min_n = min_n;
+    ctx->warm_max_n = max_n;
     return FMGMC_OK;
 }
 

@@ -384,7 +384,8 @@ int fmgmc_cnn_load(fmgmc_cnn *c, const char *path) {
 
 int fmgmc_cnn_forward(fmgmc_cnn *c, int32_t n, int64_t batch, const float *x, float *y, int32_t prec,
                       void *stream) {
-    if (!c || !x || !y || (prec != FMGMC_CNN_FP32 && prec != FMGMC_CNN_BF16)) {
+    if (!c || !x || !y || (prec != FMGMC_CNN_FP32 && prec != FMGMC_CNN_BF16 && prec != FMGMC_CNN_BF16_FUSED) ||
+        (prec == FMGMC_CNN_BF16_FUSED && batch > 65535)) {
         set_error("fmgmc_cnn_forward: bad arguments");
         return FMGMC_EINVAL;
     }
@@ -403,6 +404,16 @@ int fmgmc_cnn_forward(fmgmc_cnn *c, int32_t n, int64_t batch, const float *x, fl
         return FMGMC_OK;
     }
     TRY(cnn_ensure_packed(c, st));
+    if (prec == FMGMC_CNN_BF16_FUSED) {
+        InferArgs a{};
+        a.n = n;
+        a.S = int(batch);
+        a.in0 = x;
+        a.in1 = x + nn;
+        a.in_stride = 2 * nn;
+        a.y = y;
+        return launch_cnn_fused(a, cnn_packed(c), st);
+    }
     const int64_t per = nn * kCnnWidth * 2;  // bytes of one sample's activations
     const int sub = int(std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t(256) << 20) / per)));
     if (c->cap_act < sub * per) {

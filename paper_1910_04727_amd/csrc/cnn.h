@@ -89,14 +89,18 @@ struct InferArgs {
     int log0;
     const double *rr;     // nullable: scale1 = 1 / sqrt(rr[s] / n^2), also the output scale
     // output: y (nullable) [S][n][n] = network output; or p += scale * output
+    // (launch_cnn_infer); or e = scale * output in FP32 (launch_cnn_fused)
     float *y;
     double *p;
+    float *e;
     const int32_t *active;  // nullable
 };
 // runs all layers over S samples in sub-batches; act0/act1 hold sub_batch
 // samples of [n][n][32] bf16 each
 int launch_cnn_infer(const InferArgs &a, const CnnPacked &w, void *act0, void *act1, int sub_batch,
                      hipStream_t st);
+// all layers in one pass, activations on chip (same results as launch_cnn_infer)
+int launch_cnn_fused(const InferArgs &a, const CnnPacked &w, hipStream_t st);
 
 }  // namespace fmgmc
 

@@ -194,6 +194,210 @@ __global__ __launch_bounds__(256) void k_cnn_layer(LayerArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// All six layers in one pass. A workgroup marches up a strip of FW = 64
+// computed columns of one sample (FV = 52 valid output columns: each layer
+// narrows the valid region by one cell per side), with every layer's
+// activations for the rows in flight in LDS: a 4-row ring per hidden layer
+// ([row][1 + 64 + 1 cells][32 channels] bf16, an 80-byte cell stride as in
+// k_cnn_layer) and a 4-row ring of the two FP32 input planes. Layer k works on
+// row F - 2k at step F, two rows behind layer k - 1, so every row it reads was
+// written in an earlier step and one barrier per step orders the whole
+// pipeline. Eight waves: a pair per layer group, each wave of a pair taking
+// two of the four M-tiles, with the group's B fragments in registers for the
+// whole strip (pair 0: layers 0 and 1; pair 1: layer 2; pair 2: layer 3;
+// pair 3: layer 4; pairs 1 and 2 also take one M-tile each of the output
+// layer). Cells outside the domain are stored as zeros (the zero padding of
+// every convolution), so activations never leave the chip. The input planes
+// are loaded four rows ahead; the output is stored, never read back. The
+// fragments, the tap order and the bf16 rounding points are those of
+// k_cnn_layer, so the network output y is the same bits.
+constexpr int FW = 64;                 // computed cells per strip row
+constexpr int FV = FW - 12;            // valid output cells per strip
+constexpr int FROW = (FW + 2) * CS;    // bf16 elements of one ring row (pad cell each side)
+constexpr int FRING = 4 * FROW;        // one layer's ring
+constexpr int FPRE = 2;                // input rows in flight
+constexpr size_t fused_lds_bytes() {
+    return size_t(kCnnRes + 1) * FRING * sizeof(__bf16) + size_t(4) * (FW + 2) * 2 * sizeof(float);
+}
+
+struct FusedArgs {
+    int n;
+    const float *in0, *in1;
+    int64_t in_stride;
+    int log0;
+    const double *rr;
+    float *y;   // network output (nullable)
+    float *e;   // rms(r) * output in FP32 (nullable): the correction of the start
+    const int32_t *active;
+    const bf8 *w[kCnnLayers];
+    const float *bias[kCnnLayers];
+};
+
+__global__ __launch_bounds__(512) void k_cnn_fused(FusedArgs A) {
+    const int n = A.n, s = blockIdx.y;
+    if (A.active && A.active[s] == 0) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char fsm[];
+    __bf16 *ring = reinterpret_cast<__bf16 *>(fsm);                                    // [5][4][66][CS]
+    float *xin = reinterpret_cast<float *>(fsm + size_t(kCnnRes + 1) * FRING * sizeof(__bf16));  // [4][66][2]
+    const int t = threadIdx.x, wv = t >> 6, role = wv >> 1, half = wv & 1, l = t & 63;
+    const int gx0 = int(blockIdx.x) * FV - 6;  // global column of computed cell 0
+    const size_t nn = size_t(n) * n;
+    for (size_t e = t; e < fused_lds_bytes() / 16; e += 512) reinterpret_cast<uint4 *>(fsm)[e] = uint4{0u, 0u, 0u, 0u};
+    // this wave's weights: wa the hidden layer role + 1; wb layer 0 (role 0, entries 0 and 1)
+    // or the output layer (roles 1, 2)
+    bf8 wa[18], wb[9];
+    const int la = role + 1;
+#pragma unroll
+    for (int f = 0; f < 18; ++f) wa[f] = A.w[la][f * 64 + l];
+#pragma unroll
+    for (int f = 0; f < 9; ++f)
+        wb[f] = role == 0 ? (f < 2 ? A.w[0][f * 64 + l] : bf8{})
+                          : ((role == 1 || role == 2) ? A.w[kCnnLayers - 1][f * 64 + l] : bf8{});
+    const float bo = A.bias[kCnnLayers - 1][0];
+    const double sc = scale_of(A.rr, s, n);
+    const float inv = sc > 0.0 ? float(1.0 / sc) : 0.f;
+    // input planes: thread t < 128 owns channel t / 64 of computed cell t % 64
+    const int ich = t >> 6, ic = t & 63, igc = gx0 + ic;
+    const bool icol = t < 128 && igc >= 0 && igc < n;
+    const float *ip = (ich == 0 ? A.in0 : A.in1) + size_t(s) * A.in_stride;
+    auto load_raw = [&](int row) -> float { return (icol && row >= 0 && row < n) ? ip[size_t(row) * n + igc] : 0.f; };
+    // the network input of a loaded value (0 outside the domain: zero padding)
+    auto input = [&](float v, int row) -> float {
+        if (!icol || row < 0 || row >= n) return 0.f;
+        return ich == 0 ? (A.log0 ? __logf(v) : v) : (A.rr ? v * inv : v);
+    };
+    __syncthreads();
+    if (t < 128) xin[(ic + 1) * 2 + ich] = input(load_raw(0), 0);  // row 0 in slot 0
+    // queue of raw input rows in flight: qu holds row F + u + 1 at step F + u (F a multiple of FPRE)
+    float q0 = load_raw(1), q1 = load_raw(2);
+    __syncthreads();
+
+    // Products with the weights as the A operand (rows = output channels) and the
+    // activations as B (columns = cells): the packed fragments serve either
+    // operand, and D then gives each lane four consecutive channels of one cell
+    // (lane l, register v -> channel 16 q + 4 (l / 16) + v, cell 16 m + l % 16),
+    // so the epilogue reads the residual and writes the result 8 bytes at a time.
+    // Biases of this lane's channels: 16 q + 4 (l / 16) + v.
+    float bz[2][4], ba[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            bz[q][v] = A.bias[0][16 * q + 4 * (l >> 4) + v];
+            ba[q][v] = A.bias[la][16 * q + 4 * (l >> 4) + v];
+        }
+    typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+    // hidden layer k on row r (cell tiles 2 half, 2 half + 1) from ring k - 1 into
+    // ring k (k >= 1), or layer 0 from the input planes
+    auto hidden = [&](int k, int r, const bf8 *wk, const float (*bk)[4]) {
+        __bf16 *dst = ring + k * FRING + (r & 3) * FROW;
+        if (r < 0 || r >= n) {  // zero padding of the next layer's input (each wave its half of the row)
+            for (int e = l + 64 * half; e < FROW / 8; e += 128) reinterpret_cast<uint4 *>(dst)[e] = uint4{0u, 0u, 0u, 0u};
+            return;
+        }
+        f4 acc[2][2];  // [channel tile q][cell tile m]
+#pragma unroll
+        for (int m = 0; m < 2; ++m) acc[0][m] = acc[1][m] = f4{0.f, 0.f, 0.f, 0.f};
+        if (k == 0) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                bf8 a;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int kk = 8 * (l >> 4) + e;
+                    float v = 0.f;
+                    if (kk < 18) {
+                        const int tap = kk >> 1;
+                        v = xin[(((r + tap / 3 - 1) & 3) * (FW + 2) + 16 * (2 * half + m) + (l & 15) + tap % 3) * 2 + (kk & 1)];
+                    }
+                    a[e] = __bf16(v);
+                }
+                acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wk[0], a, acc[0][m], 0, 0, 0);
+                acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wk[1], a, acc[1][m], 0, 0, 0);
+            }
+        } else {
+            const __bf16 *src = ring + (k - 1) * FRING;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const __bf16 *srow = src + ((r + tap / 3 - 1) & 3) * FROW;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const bf8 a = *reinterpret_cast<const bf8 *>(srow + (16 * (2 * half + m) + (l & 15) + tap % 3) * CS +
+                                                                8 * (l >> 4));
+                    acc[0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wk[2 * tap], a, acc[0][m], 0, 0, 0);
+                    acc[1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wk[2 * tap + 1], a, acc[1][m], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue: bias, ReLU, the residual (k >= 1), zeros outside the domain
+        const __bf16 *res = ring + (k > 0 ? k - 1 : 0) * FRING + (r & 3) * FROW;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int c = 16 * (2 * half + m) + (l & 15), gc = gx0 + c;
+            const bool in = gc >= 0 && gc < n;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int ch = 16 * q + 4 * (l >> 4);
+                bf4 rv = bf4{};
+                if (k > 0) rv = *reinterpret_cast<const bf4 *>(res + (c + 1) * CS + ch);
+                bf4 out;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float z = acc[q][m][v] + bk[q][v];
+                    z = z > 0.f ? z : 0.f;
+                    if (k > 0) z += float(rv[v]);
+                    out[v] = __bf16(in ? z : 0.f);
+                }
+                *reinterpret_cast<bf4 *>(dst + (c + 1) * CS + ch) = out;
+            }
+        }
+    };
+    // output layer on row r for cell tile m (one channel tile; channel 0 is the output,
+    // held by lanes 0..15 in register 0)
+    auto output = [&](int r, int m) {
+        if (r < 0 || r >= n) return;
+        const __bf16 *src = ring + kCnnRes * FRING;
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const __bf16 *srow = src + ((r + tap / 3 - 1) & 3) * FROW;
+            const bf8 a = *reinterpret_cast<const bf8 *>(srow + (16 * m + (l & 15) + tap % 3) * CS + 8 * (l >> 4));
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[tap], a, acc, 0, 0, 0);
+        }
+        if (l >= 16) return;
+        const int c = 16 * m + l, gc = gx0 + c;
+        if (c < 6 || c >= 6 + FV || gc >= n) return;
+        const size_t o = size_t(s) * nn + size_t(r) * n + gc;
+        const float yv = acc[0] + bo;
+        if (A.y) A.y[o] = yv;
+        if (A.e) A.e[o] = float(sc * double(yv));
+    };
+    const int last = n - 1 + 2 * (kCnnLayers - 1);
+    for (int F = 0; F <= last; F += FPRE) {
+        // FPRE steps per iteration so that the input queue slots are constants:
+        // at step F + u the queue slot q_u holds row F + u + 1 and takes row F + u + 1 + FPRE
+#define FMGMC_FUSED_STEP(u, qv)                                                                     \
+        if (F + u <= last) {                                                                         \
+            const int Fs = F + u;                                                                    \
+            if (t < 128) xin[((((Fs + 1) & 3) * (FW + 2)) + ic + 1) * 2 + ich] = input(qv, Fs + 1); \
+            qv = load_raw(Fs + 1 + FPRE);                                                            \
+            __syncthreads();                                                                         \
+            if (role == 0) {                                                                         \
+                hidden(0, Fs, wb, bz);                                                               \
+                hidden(1, Fs - 2, wa, ba);                                                           \
+            } else {                                                                                 \
+                hidden(la, Fs - 2 * la, wa, ba);                                                     \
+                if (role == 1) output(Fs - 2 * (kCnnLayers - 1), half);                              \
+                if (role == 2) output(Fs - 2 * (kCnnLayers - 1), 2 + half);                          \
+            }                                                                                        \
+        }
+        FMGMC_FUSED_STEP(0, q0)
+        FMGMC_FUSED_STEP(1, q1)
+#undef FMGMC_FUSED_STEP
+    }
+}
+
 // Fragment packing from the FP32 parameter vector (layout of cnn.h).
 __global__ void k_pack_first(const float *W, bf8 *frag) {
     const int l = threadIdx.x & 63, q = threadIdx.x >> 6;  // 128 threads
@@ -284,6 +488,42 @@ int launch_pack_weights(const float *theta, void *const *wfrag, float *const *bi
                                static_cast<bf8 *>(wfrag[l]), co == 1 ? 1 : 2);
         hipLaunchKernelGGL(k_copy_f32, dim3(1), dim3(64), 0, st, W + size_t(co) * ci * 9, bias[l], co);
     }
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
+}
+
+int launch_cnn_fused(const InferArgs &a, const CnnPacked &w, hipStream_t st) {
+    const int n = a.n;
+    if (n < 16 || (n & (n - 1)) || n > 1024 || a.S > 65535) {
+        set_error("launch_cnn_fused: n must be a power of two in [16, 1024], at most 65535 samples");
+        return FMGMC_EINVAL;
+    }
+    if (a.S <= 0) return FMGMC_OK;
+    static bool attr_set = false;  // the kernel's LDS exceeds the default dynamic limit
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_cnn_fused),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(fused_lds_bytes())) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("launch_cnn_fused: cannot raise the kernel's LDS limit");
+            return FMGMC_EHIP;
+        }
+        attr_set = true;
+    }
+    FusedArgs f{};
+    f.n = n;
+    f.in0 = a.in0;
+    f.in1 = a.in1;
+    f.in_stride = a.in_stride;
+    f.log0 = a.log0;
+    f.rr = a.rr;
+    f.y = a.y;
+    f.e = a.e;
+    f.active = a.active;
+    for (int k = 0; k < kCnnLayers; ++k) {
+        f.w[k] = static_cast<const bf8 *>(w.w[k]);
+        f.bias[k] = w.b[k];
+    }
+    const dim3 grid((n + FV - 1) / FV, a.S);
+    hipLaunchKernelGGL(k_cnn_fused, grid, dim3(512), fused_lds_bytes(), st, f);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 

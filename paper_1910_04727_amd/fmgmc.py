@@ -42,7 +42,8 @@ class Opts(C.Structure):
                 ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("inner_cycles", C.c_int32),
                 ("max_batch", C.c_int32), ("w_max_n", C.c_int32), ("rel_tol", C.c_double),
                 ("inner_first", C.c_int32), ("separate_coarse", C.c_int32), ("fuse_cycles", C.c_int32),
-                ("warm", C.c_int32), ("warm_min_n", C.c_int32), ("cnn_weights", C.c_char_p),
+                ("warm", C.c_int32), ("warm_min_n", C.c_int32), ("warm_max_n", C.c_int32),
+                ("cnn_weights", C.c_char_p),
                 ("tune_cache", C.c_char_p)]
 
 
@@ -97,6 +98,7 @@ _SIGS = {
     "fmgmc_cnn_make_data": (C.c_int, [_VP, C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fmgmc_cnn_train": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, _VP, C.c_int32, C.c_double, _VP]),
     "fmgmc_set_warm_start": (C.c_int, [_VP, _VP, C.c_int32]),
+    "fmgmc_set_warm_range": (C.c_int, [_VP, _VP, C.c_int32, C.c_int32]),
     "fmgmc_last_error": (C.c_char_p, []),
     "fmgmc_version": (C.c_int, []),
 }
@@ -164,7 +166,7 @@ class Context:
                  nu1=2, nu2=2, max_cycles=50, inner_cycles=1, max_batch=0, rel_tol=1e-10,
                  p_west=None, p_east=None, device=0, w_max_n=64, inner_first=0, separate_coarse=False,
                  case=2, p_south=None, p_north=None, fuse_cycles=True, cnn_weights=None, warm_min_n=0,
-                 tune_cache=None):
+                 warm_max_n=0, tune_cache=None):
         if case not in BOUNDARY_DEFAULTS:
             raise ValueError("case must be 1 or 2 (Table 1)")
         g = [d if v is None else float(v) for d, v in zip(BOUNDARY_DEFAULTS[case], (p_west, p_east, p_south, p_north))]
@@ -173,7 +175,7 @@ class Context:
         self.hier = Hier(n_levels, n0, 4, 1 if case == 1 else 0, *g)
         self.opts = Opts(SOLVERS[solver], KL_PREC[kl_prec], nu1, nu2, max_cycles, inner_cycles,
                          max_batch, w_max_n, rel_tol, inner_first, 1 if separate_coarse else 0,
-                         1 if fuse_cycles else 0, 1 if cnn_weights is not None else 0, warm_min_n,
+                         1 if fuse_cycles else 0, 1 if cnn_weights is not None else 0, warm_min_n, warm_max_n,
                          None if cnn_weights is None else os.fsencode(cnn_weights),
                          None if tune_cache is None else os.fsencode(tune_cache))
         self.n_modes = n_modes
@@ -269,10 +271,10 @@ class Context:
         return dict(check_every=int(p[0]), graphs=int(p[1]), batch=int(p[2]))
 
 
-    def set_warm_start(self, cnn, min_n=256):
-        """Warm-start QoI stages with n >= min_n from `cnn` (None: off)."""
+    def set_warm_start(self, cnn, min_n=256, max_n=0):
+        """Warm-start QoI stages with min_n <= n <= max_n (0: no bound) from `cnn` (None: off)."""
         self._warm = cnn  # keep the network alive while the context uses it
-        _check(lib().fmgmc_set_warm_start(self._h, cnn._h if cnn is not None else None, min_n))
+        _check(lib().fmgmc_set_warm_range(self._h, cnn._h if cnn is not None else None, min_n, max_n))
 
     def make_data(self, level, xi, x_coarse, t_coarse, x_fine, t_fine, stream=None):
         """Training pairs of the two QoI stages (device float32 buffers)."""
@@ -349,7 +351,7 @@ class Cnn:
         _check(lib().fmgmc_cnn_adam(self._h, lr, _stream_ptr(stream)))
 
 
-CNN_PREC = {"fp32": 0, "bf16": 1}
+CNN_PREC = {"fp32": 0, "bf16": 1, "bf16_fused": 2}
 CNN_LOSS = {"error": 0, "residual": 1}
 
 

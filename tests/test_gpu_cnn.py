@@ -203,3 +203,25 @@ def test_trained_network_saves_cycles_and_keeps_every_q():
     # both starts end at rel-res <= 1e-10: the QoIs agree to the accuracy of the stopping rule
     assert np.max(np.abs(w[1] - p[1]) / np.abs(p[1])) <= 1e-7
     assert np.max(np.abs(w[2] - p[2]) / np.abs(p[2])) <= 1e-7
+
+
+@pytest.mark.parametrize("n,B", [(16, 3), (64, 2), (128, 2), (512, 1)])
+def test_fused_inference_equals_per_layer(n, B):
+    """All six layers in one on-chip pass (row strips of 52 valid columns, several
+    strips from 64^2 up) against one launch per layer: the same fragments, tap
+    order and bf16 rounding points, so the same bits; and the oracle forward."""
+    th, x, _ = seeded(41 + n, B, n, 0.1)
+    with fmgmc.Cnn() as net:
+        net.set_params(th)
+        xd = dev(x)
+        y1 = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+        y2 = torch.full_like(y1, float("nan"))
+        net.forward(xd, y1, prec="bf16")
+        net.forward(xd, y2, prec="bf16_fused")
+        torch.cuda.synchronize()
+    a, b = y1.cpu().numpy(), y2.cpu().numpy()
+    log(f"fused n {n}: max |fused - per-layer| {np.abs(a - b).max():.3e}")
+    assert np.array_equal(a, b)
+    if n <= 128:
+        yo = O.cnn_forward(th.astype(np.float64), x)
+        assert np.abs(b - yo).max() / np.abs(yo).max() <= 3e-2
