@@ -189,13 +189,41 @@ def qoi_err(form, ref):
 # benchmark after the headline so that every configuration is measured in the
 # same run. Each entry states what was reduced relative to the full workload.
 
-def _kl_mfma(prof, dtype):
-    ms, n, flops = prof["kl"]
-    if not n or ms <= 0:
+def _kl_write_bytes(n):
+    """Coefficient bytes the KL pass writes per sample in an FP32+IR solve whose finest grid
+    is n: the FP64 field on the two top grids, the FP32 field on every grid down to 4^2."""
+    grids = [n >> k for k in range((n // 4).bit_length())]
+    return 8 * (grids[0] ** 2 + grids[1] ** 2) + 4 * sum(g * g for g in grids)
+
+
+def _kl_mfma(prof, dtype, samples=0, n=0):
+    ms, launches, flops = prof["kl"]
+    if not launches or ms <= 0:
         return None
     peak = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}[dtype]
     tf = flops / (ms * 1e-3) / 1e12
-    return {"tflops": round(tf, 2), "peak_tflops": peak, "frac": round(tf / peak, 4), "ms": round(ms, 3)}
+    out = {"tflops": round(tf, 2), "peak_tflops": peak, "frac": round(tf / peak, 4), "ms": round(ms, 3)}
+    if samples and n:
+        gbs = _kl_write_bytes(n) * samples / (ms * 1e-3) / 1e9
+        out.update(write_gbs=round(gbs, 1), hbm_frac=round(gbs / 8000.0, 4),
+                   ms_at_hbm_peak=round(_kl_write_bytes(n) * samples / 8e12 * 1e3, 3))
+    return out
+
+
+def _fill_gbs(torch, nbytes, reps=3):
+    """Rate of a plain device fill of nbytes (a store-only reference for the KL writes)."""
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    buf.fill_(0.0)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        buf.fill_(1.0)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del buf
+    return round(nbytes / (ms * 1e-3) / 1e9, 1)
 
 
 def compact_reports(torch, fmgmc, inputs, args):
@@ -290,7 +318,7 @@ def compact_reports(torch, fmgmc, inputs, args):
             ctx.profile(False)
             pr = ctx.profile_read()
             if l == cfg["n_levels"] - 1:
-                kl_rate[k] = _kl_mfma(pr, prec[k])
+                kl_rate[k] = _kl_mfma(pr, prec[k], Np, cfg["n0"] << l)
             q[k] = torch.cat([qf, qc]).cpu().numpy()
             if k == "kl_fp64":
                 e = fmgmc.estimate([qf], [qc], n_shifts=R)
@@ -311,10 +339,16 @@ def compact_reports(torch, fmgmc, inputs, args):
     for c in ctxs.values():
         c.close()
     d3["variance_ratio_mc_over_rqmc_total"] = tot["var_mc"] / tot["var_rqmc"]
+    n_top = cfg["n0"] << (cfg["n_levels"] - 1)
     d3["kl_contraction_at_512"] = {
         "note": "KL synthesis rate on the 512^2 level (FP64: the separable factorisation; FP32 / BF16: the dense "
                 "samples x 512 modes x cells contraction with FP32 accumulation), flops of the path taken over "
-                "the kernel's event-timed duration, against the dense matrix-core peak of its input type",
+                "the kernel's event-timed duration, against the dense matrix-core peak of its input type; "
+                "write_gbs: the coefficient pyramid it writes over the same duration, against 8 TB/s "
+                "(ms_at_hbm_peak: the bound those writes set); plain_fill_gbs: a store-only device fill of "
+                "one launch's bytes",
+        "bytes_written_per_sample": _kl_write_bytes(n_top),
+        "plain_fill_gbs": _fill_gbs(torch, _kl_write_bytes(n_top) * 2048),
         **{k: v for k, v in kl_rate.items()}}
     out["d3_cfg3"] = d3
     log("reports: d3 done")
@@ -850,8 +884,53 @@ def report_adaptive(torch, fmgmc, inputs, args):
                                    "2^m x 16 shifts doubled per level"}}
 
 
+def report_kl(torch, fmgmc, inputs, args):
+    """KL synthesis on the 512^2 level of the cfg3 field (512 modes) inside FP32+IR solves:
+    FP64 (separable factorisation), FP32 and BF16 (dense contraction, FP32 accumulation).
+    Per launch: the event-timed kernel duration, its matrix-core rate against the dense
+    peak of its input type, and its coefficient writes (the FP64 field on the two top
+    grids, the FP32 field on every grid of the pyramid) against HBM bandwidth."""
+    cfg = dict(sigma2=2.0, corr_len=0.1, n_modes=512, n_levels=4, n0=64)
+    level, S, batch = 3, args.samples, min(args.batch, 2048)
+    n = cfg["n0"] << level
+    xi = _dev(torch, inputs.mc_normals_blocked(0, S, cfg["n_modes"], config=3, level=level))
+    per_sample = _kl_write_bytes(n)
+    peak = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+    out, q = {}, {}
+    for p in ("fp64", "fp32", "bf16"):
+        with fmgmc.Context(**cfg, solver="fp32_ir", kl_prec=p, max_batch=batch, max_cycles=60) as ctx:
+            qf, qc, c, fl = _bufs(torch, S)
+            for _ in range(args.warmup):
+                ctx.solve_level(level, xi, qf, qc, c, fl)
+            ctx.profile(True)
+            for _ in range(args.steps):
+                ctx.solve_level(level, xi, qf, qc, c, fl)
+            torch.cuda.synchronize()
+            ctx.profile(False)
+            ms, launches, flops = ctx.profile_read()["kl"]
+            q[p] = qf.cpu().numpy()
+        per_launch = ms / launches
+        samples = S * args.steps / launches
+        gbs = per_sample * samples / (per_launch * 1e-3) / 1e9
+        tf = flops / (ms * 1e-3) / 1e12
+        out[p] = {"ms_per_launch": round(per_launch, 4), "samples_per_launch": samples,
+                  "tflops": round(tf, 2), "mfma_peak_tflops": peak[p], "mfma_frac": round(tf / peak[p], 4),
+                  "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / 8000.0, 4),
+                  "path": "separable" if p == "fp64" else "dense"}
+        if p != "fp64":
+            out[p]["qoi_rel_diff_vs_fp64_kl"] = _rel(q[p], q["fp64"])
+        log(f"kl {p}: {per_launch:.3f} ms per launch, {tf:.1f} TFLOP/s, {gbs:.0f} GB/s of field writes")
+    fill = _fill_gbs(torch, per_sample * batch)
+    for p in out:
+        out[p]["frac_of_plain_fill"] = round(out[p]["write_gbs"] / fill, 4)
+    return {"metric": "KL synthesis rate on the 512^2 level", "value": out["bf16"]["tflops"], "unit": "TFLOP/s (BF16)",
+            "precisions": out, "bytes_written_per_sample": per_sample, "plain_fill_gbs": fill,
+            "config": {"workload": f"cfg3 field (sigma2=2, corr_len=0.1, 512 modes), 512^2 level, {S} samples in "
+                                   f"launches of {batch}, inside FP32+IR solves", "steps": args.steps}}
+
+
 REPORTS = {"case1": report_case1, "cfg1": report_cfg1, "saving": report_saving, "adaptive": report_adaptive, "cfg2": report_cfg2, "cfg3": report_cfg3, "cfg4": report_cfg4,
-           "cfg5": report_cfg5}
+           "cfg5": report_cfg5, "kl": report_kl}
 
 
 def main():

@@ -116,6 +116,7 @@ struct Work {
     Pyr<float> pf32[2];
     double *chol = nullptr;  // [3][S][N0*N0]: inverses of stage op, coarse-stage pyramid, fine-stage pyramid
     double *rr = nullptr, *q = nullptr, *bnorm = nullptr, *qf = nullptr, *qc = nullptr, *xi = nullptr;
+    unsigned char *klx = nullptr;  // xi in matrix-core operand order (FP32 / BF16 KL contraction)
     int32_t *active = nullptr, *cycles = nullptr, *n_active = nullptr;
     uint8_t *flags = nullptr;
     int32_t *h_n_active = nullptr;  // pinned, 2 slots (cycle blocks in flight)
@@ -149,6 +150,7 @@ void free_work(Work &w) {
         }
     }
     dfree(w.chol); dfree(w.rr); dfree(w.q); dfree(w.bnorm); dfree(w.qf); dfree(w.qc); dfree(w.xi);
+    dfree(w.klx);
     dfree(w.active); dfree(w.cycles); dfree(w.n_active); dfree(w.flags);
     for (int k = 0; k < 2; ++k)
         if (w.act[k]) (void)hipFree(w.act[k]);
@@ -260,6 +262,7 @@ int alloc_work(const fmgmc_ctx *c, Work &w, int S, int n_top) {
     TRY(dalloc(&w.chol, size_t(3) * S * N0 * N0));
     TRY(dalloc(&w.rr, S)); TRY(dalloc(&w.q, S)); TRY(dalloc(&w.bnorm, S));
     TRY(dalloc(&w.qf, S)); TRY(dalloc(&w.qc, S)); TRY(dalloc(&w.xi, size_t(S) * M));
+    TRY(dalloc(&w.klx, kl_work_bytes(S, M, c->opts.kl_prec)));
     TRY(dalloc(&w.active, S)); TRY(dalloc(&w.cycles, 2 * size_t(S))); TRY(dalloc(&w.n_active, 1));
     TRY(dalloc(&w.flags, S));
     TRY(dalloc(&w.rr0, S));
@@ -871,6 +874,7 @@ int solve_level_on(fmgmc_ctx *ctx, Work &W, const Tune &tn, int level, int64_t n
         a.ma = ctx->d_ma;
         a.mb = ctx->d_mb;
         a.sqrtlam = ctx->d_sqrtlam;
+        a.xw = W.klx;
         a.nlev = t + 1;
         for (int j = 0; j <= t; ++j) {
             const int k = t - j;  // pyramid slot j = grid index t - j
@@ -1146,6 +1150,7 @@ int fmgmc_synthesize_field(fmgmc_ctx *ctx, int32_t level, int64_t n_samples, con
         a.ma = ctx->d_ma;
         a.mb = ctx->d_mb;
         a.sqrtlam = ctx->d_sqrtlam;
+        a.xw = ctx->main.klx;
         a.nlev = 1;
         a.K64[0] = k_dev ? k_out + size_t(s0) * n * n : tmp;
         rc = launch_kl(a, S, ctx->opts.kl_prec, st);

@@ -134,7 +134,10 @@ struct KLArgs {
     int nlev;             // pyramid levels written (finest first): n, n/2, ...
     double *K64[9];       // nullable per level
     float *K32[9];        // nullable per level
+    void *xw;             // FP32 / BF16 contraction: xi in operand order, kl_work_bytes(S, M, prec) bytes
 };
+// device bytes of the xi workspace launch_kl needs for S samples (0: none)
+size_t kl_work_bytes(int S, int M, int prec);
 int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st);
 // whether launch_kl takes the separable path, and its flops per sample
 bool kl_separable(const KLArgs &a, int prec);

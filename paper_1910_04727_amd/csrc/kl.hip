@@ -3,8 +3,8 @@
 //   g[s][c] = sum_m xi[s][m] * B[m][c],
 //   B[m][c] = sqrt(lambda_m) phi_{a_m}(x_i) phi_{b_m}(y_j),  c = j n + i,
 //   K = exp(g) at the cell lower-left corners (x_i, y_j) = (i/n, j/n).
-// B is never stored in HBM: each workgroup builds its 64-mode x 64-cell slice
-// of it in LDS from the 1-D eigenfunction tables. The epilogue applies exp
+// B is never stored in HBM: each workgroup builds the slice of it that its
+// cells need in LDS from the 1-D eigenfunction tables. The epilogue applies exp
 // and writes every level of the injected coefficient pyramid
 // (Section 2.5, Coarsening): cell (i, j) of the fine grid also serves as cell
 // (i/2^k, j/2^k) of level k whenever 2^k divides both i and j.
@@ -137,60 +137,6 @@ __global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
             store_pyramid(A, S, s0 + 16 * w + 4 * v + (l >> 4), c0 + 16 * q + (l & 15), acc[q][v], false);
 }
 
-// FP32: v_mfma_f32_16x16x4_f32, same operand layout as the FP64 form; output
-// register v of lane l holds row 4 (l/16) + v, column l%16.
-__global__ __launch_bounds__(256) void k_kl_f32(KLArgs A, int S) {
-    constexpr int XSTR = xstr<float>();
-    __shared__ float Xs[TS * XSTR];
-    __shared__ float Bt[TM * BSTR];
-    extern __shared__ double rowf[];  // [M] then int ia[M]
-    int *ia = reinterpret_cast<int *>(rowf + A.M);
-    const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    const bool row = stage_row(A, c0, rowf, ia);
-    __syncthreads();
-    const double *rf = row ? rowf : nullptr;
-    float xr[PER], br[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        xr[k] = float(xi_elem(A, S, s0, 0, t + 256 * k));
-        br[k] = float(b_elem(A, 0, c0, t + 256 * k, rf, ia));
-    }
-    f4 acc[4];
-    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int m0 = 0; m0 < A.M; m0 += TM) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = t + 256 * k;
-            Xs[(e / TM) * XSTR + e % TM] = xr[k];
-            Bt[(e / TC) * BSTR + e % TC] = br[k];
-        }
-        __syncthreads();
-        if (m0 + TM < A.M) {
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                xr[k] = float(xi_elem(A, S, s0, m0 + TM, t + 256 * k));
-                br[k] = float(b_elem(A, m0 + TM, c0, t + 256 * k, rf, ia));
-            }
-        }
-#pragma unroll 4
-        for (int kk = 0; kk < TM / 4; ++kk) {
-            const float a = Xs[(16 * w + (l & 15)) * XSTR + 4 * kk + (l >> 4)];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float b = Bt[(4 * kk + (l >> 4)) * BSTR + 16 * q + (l & 15)];
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            store_pyramid(A, S, s0 + 16 * w + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), double(acc[q][v]), true);
-}
-
 // ---------------------------------------------------------------- separable
 // For the separable covariance every 2-D mode is a product of 1-D modes
 // (Section 3.1 (2)), so the same sum factors through a small per-sample matrix:
@@ -300,56 +246,219 @@ size_t sep_lds() {
     return size_t(AP) * TSTR * sizeof(double);  // C_s ([AP][AP+2]) and T ([AP][TSTR]) share it
 }
 
-// BF16 inputs, FP32 accumulation: v_mfma_f32_16x16x32_bf16. Lane l holds
-// A[row l%16][k = 8 (l/16) .. +7] and B[k = 8 (l/16) .. +7][col l%16]; D as above.
+// ------------------------------------------------------ dense, FP32 / BF16 inputs
+// v_mfma_f32_16x16x4_f32 (FP32) and v_mfma_f32_16x16x32_bf16 (BF16), FP32
+// accumulation. Both operands are kept in the order the matrix cores take
+// them, in 16-byte lane slots. Slot kc of a group of 16 rows (samples) or
+// columns (cells) gives lane l = r + 16 h (row or column r) the modes
+//   BF16, one K-step of 32 modes:   32 kc + 8 h + e,  e < 8,
+//   FP32, four K-steps of 4 modes:  16 kc + 4 e + h,  e < 4 (element e feeds K-step 4 kc + e),
+// so that every operand fetch of a wave is one contiguous 1 KB read. Each
+// operand is rounded once, from FP64 to the input type (to nearest, ties to
+// even; for BF16 not through FP32, which could round twice). xi is
+// converted into that order once per launch (k_kl_xcvt, zero-padded to whole
+// 16-sample groups and to a multiple of 32 modes). The Phi slice of a
+// workgroup's 64 cells is built once in LDS (sqrt(lambda_m) phi_a(x_i)
+// phi_b(y_j) in FP64) and reused for every sample
+// tile the workgroup owns, so the gathers and FP64 products behind it are paid
+// once per cell and mode, not once per sample tile. The A operand (xi) is read
+// straight from L2 ahead of its use. Eight waves take 32 samples x 64 cells
+// each (two 16-sample groups x four 16-cell groups, 8 accumulators).
+// After the contraction the pass writes 12 bytes per fine cell and sample
+// (FP64 and FP32 fields) plus the pyramid, and is bound by those writes.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-__global__ __launch_bounds__(256) void k_kl_bf16(KLArgs A, int S) {
-    __shared__ __bf16 Xs[TS * (TM + 8)];
-    __shared__ __bf16 Bt[TC * (TM + 8)];   // transposed: [cell][mode]
-    const int c0 = blockIdx.x * TC, s0 = blockIdx.y * TS;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    f4 acc[4];
-    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+template <typename T> struct Lp;
+template <> struct Lp<float> {
+    typedef f4 V;
+    static constexpr int CM = 16;  // modes per slot
+    __device__ static int mode(int h, int e) { return 4 * e + h; }
+};
+template <> struct Lp<__bf16> {
+    typedef bf8 V;
+    static constexpr int CM = 32;
+    __device__ static int mode(int h, int e) { return 8 * h + e; }
+};
+constexpr int LP_WAVES = 8;              // waves per workgroup
+constexpr int LP_TILE = 32 * LP_WAVES;   // samples per sample tile
+constexpr int LP_SLOTS = 32;             // Phi slots held in LDS at once (32 x 4 KB)
+constexpr int LP_MPAD = 32;              // modes padded to a multiple of this
+
+int lp_chunks(int M, int prec) {
+    const int mp = (M + LP_MPAD - 1) / LP_MPAD * LP_MPAD;
+    return mp / (prec == FMGMC_KL_BF16 ? Lp<__bf16>::CM : Lp<float>::CM);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_kl_xcvt(const double *xi, int S, int M, int nch, typename Lp<T>::V *out) {
+    constexpr int EPS = 16 / sizeof(T);
+    const int64_t slot = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (slot >= int64_t((S + 15) / 16) * nch * 64) return;
+    const int l = int(slot & 63), kc = int((slot >> 6) % nch);
+    const int64_t s = 16 * ((slot >> 6) / nch) + (l & 15);
+    typename Lp<T>::V v;
+#pragma unroll
+    for (int e = 0; e < EPS; ++e) {
+        const int m = Lp<T>::CM * kc + Lp<T>::mode(l >> 4, e);
+        v[e] = T((s < S && m < M) ? xi[s * M + m] : 0.0);
+    }
+    out[slot] = v;
+}
+
+__device__ __forceinline__ void lp_mma(f4 (&acc)[2][4], const f4 &a0, const f4 &a1, const f4 (&b)[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[0][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], b[q][e], acc[0][q], 0, 0, 0);
+            acc[1][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], b[q][e], acc[1][q], 0, 0, 0);
+        }
+}
+__device__ __forceinline__ void lp_mma(f4 (&acc)[2][4], const bf8 &a0, const bf8 &a1, const bf8 (&b)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc[0][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[q], acc[0][q], 0, 0, 0);
+        acc[1][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[q], acc[1][q], 0, 0, 0);
+    }
+}
+
+// epilogue for one (sample, cell): K = exp(g), the fine field streamed out (it is
+// read back only by later passes), the coarse levels by the cells with both
+// indices even
+__device__ __forceinline__ void lp_store(const KLArgs &A, int S, int s, int c, float g) {
     const int n = A.n;
-    for (int m0 = 0; m0 < A.M; m0 += TM) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < TS * TM; e += blockDim.x) {
-            const int ss = e / TM, mm = e % TM, s = s0 + ss, m = m0 + mm;
-            const double v = (s < S && m < A.M) ? A.xi[size_t(s) * A.M + m] : 0.0;
-            Xs[ss * (TM + 8) + mm] = __bf16(float(v));
+    if (s >= S || c >= n * n) return;
+    const int i = c % n, j = c / n;
+    const float kf = __expf(g);
+    const double kv = double(kf);
+    const size_t o = size_t(s) * n * n + c;
+    if (A.K64[0]) __builtin_nontemporal_store(kv, A.K64[0] + o);
+    if (A.K32[0]) __builtin_nontemporal_store(kf, A.K32[0] + o);
+    if (!((i | j) & 1)) store_coarse(A, s, i, j, kv);
+}
+
+// Workgroup: cells c0 .. c0+63, samples [blockIdx.y sg, +sg) in tiles of LP_TILE.
+// The A slots of a wave stream through a ring of PF registers, PF slots ahead of
+// their use (three for BF16, whose K-step is a quarter of the FP32 one's
+// matrix-core time; one for FP32).
+template <typename T>
+__global__ __launch_bounds__(64 * LP_WAVES) void k_kl_lp(KLArgs A, int S, int sg, int nch) {
+    typedef typename Lp<T>::V V;
+    constexpr int CM = Lp<T>::CM, EPS = 16 / sizeof(T), PF = sizeof(T) == 2 ? 3 : 1;
+    extern __shared__ __align__(16) unsigned char lp_lds[];
+    V *Bs = reinterpret_cast<V *>(lp_lds);  // [slot][16-cell group q][lane]
+    const int n = A.n, nn = n * n, M = A.M;
+    const int c0 = blockIdx.x * 64, sb = blockIdx.y * sg, se = min(S, sb + sg);
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const V *X = static_cast<const V *>(A.xw);
+    // slice builder: thread t fills the slots of cell group bq, lane l, every other slot
+    const int bq = w & 3, bh = w >> 2, bc = c0 + 16 * bq + (l & 15);
+    const bool bval = bc < nn;
+    const int bi = bval ? bc % n : 0, bj = bval ? bc / n : 0;
+    auto build = [&](int kb0, int nb) {
+        for (int k = bh; k < nb; k += 2) {
+            V v;
+#pragma unroll
+            for (int e = 0; e < EPS; ++e) {
+                const int m = CM * (kb0 + k) + Lp<T>::mode(l >> 4, e);
+                double b = 0.0;
+                if (bval && m < M)
+                    b = A.sqrtlam[m] * A.phi[size_t(A.ma[m]) * n + bi] * A.phi[size_t(A.mb[m]) * n + bj];
+                v[e] = T(b);
+            }
+            Bs[(k * 4 + bq) * 64 + l] = v;
         }
-        for (int e = threadIdx.x; e < TM * TC; e += blockDim.x) {
-            const int mm = e / TC, cc = e % TC, m = m0 + mm, c = c0 + cc;
-            double v = 0.0;
-            if (m < A.M && c < n * n)
-                v = A.sqrtlam[m] * A.phi[size_t(A.ma[m]) * n + (c % n)] * A.phi[size_t(A.mb[m]) * n + (c / n)];
-            Bt[cc * (TM + 8) + mm] = __bf16(float(v));
-        }
+    };
+    const bool resident = nch <= LP_SLOTS;
+    if (resident) {
+        build(0, nch);
         __syncthreads();
+    }
+    const V zero = V{};
+    for (int st = sb; st < se; st += LP_TILE) {
+        const int s0 = st + 32 * w;
+        const bool act = s0 < se, two = s0 + 16 < se;
+        f4 acc[2][4];
 #pragma unroll
-        for (int kk = 0; kk < TM / 32; ++kk) {
-            bf8 a, b;
-            const __bf16 *pa = Xs + (16 * w + (l & 15)) * (TM + 8) + 32 * kk + 8 * (l >> 4);
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) a[e] = pa[e];
+            for (int q = 0; q < 4; ++q) acc[r][q] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int kb0 = 0; kb0 < nch; kb0 += LP_SLOTS) {
+            const int nb = min(LP_SLOTS, nch - kb0);
+            if (!resident) {
+                __syncthreads();
+                build(kb0, nb);
+                __syncthreads();
+            }
+            if (!act) continue;
+            const V *x0 = X + (size_t(s0 / 16) * nch + kb0) * 64 + l;
+            const V *x1 = x0 + size_t(nch) * 64;
+            V r0[PF], r1[PF];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const __bf16 *pb = Bt + (16 * q + (l & 15)) * (TM + 8) + 32 * kk + 8 * (l >> 4);
+            for (int j = 0; j < PF; ++j) {
+                r0[j] = j < nb ? x0[j * 64] : zero;
+                r1[j] = (j < nb && two) ? x1[j * 64] : zero;
+            }
+            for (int k0 = 0; k0 < nb; k0 += PF) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) b[e] = pb[e];
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+                for (int j = 0; j < PF; ++j) {
+                    const int k = k0 + j;
+                    if (k < nb) {
+                        const V a0 = r0[j], a1 = r1[j];
+                        if (k + PF < nb) {
+                            r0[j] = x0[(k + PF) * 64];
+                            if (two) r1[j] = x1[(k + PF) * 64];
+                        }
+                        V b[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) b[q] = Bs[(k * 4 + q) * 64 + l];
+                        lp_mma(acc, a0, a1, b);
+                    }
+                }
             }
         }
+        if (!act) continue;
+        // lane l holds rows 4 (l/16) + v, column l%16 of each 16 x 16 output
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    lp_store(A, S, s0 + 16 * r + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), acc[r][q][v]);
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            store_pyramid(A, S, s0 + 16 * w + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), double(acc[q][v]), true);
+}
+
+template <typename T>
+int launch_lp(const KLArgs &a, int S, int prec, hipStream_t st) {
+    typedef typename Lp<T>::V V;
+    const int nch = lp_chunks(a.M, prec);
+    const size_t lds = size_t(std::min(nch, LP_SLOTS)) * 4 * 64 * sizeof(V);
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_kl_lp<T>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       int(size_t(LP_SLOTS) * 4 * 64 * sizeof(V)));
+    if (attr != hipSuccess) {
+        set_error("launch_kl: cannot raise the kernel's LDS limit");
+        return FMGMC_EHIP;
+    }
+    const int64_t slots = int64_t((S + 15) / 16) * nch * 64;
+    hipLaunchKernelGGL(k_kl_xcvt<T>, dim3(unsigned((slots + 255) / 256)), dim3(256), 0, st, a.xi, S, a.M, nch,
+                       static_cast<V *>(a.xw));
+    // enough workgroups to fill the chip; each keeps its Phi slice for as many
+    // sample tiles as that allows
+    const int nct = (a.n * a.n + 63) / 64, tiles = (S + LP_TILE - 1) / LP_TILE;
+    const int groups = std::max(1, std::min(tiles, (1024 + nct - 1) / nct));
+    const int sg = (tiles + groups - 1) / groups * LP_TILE;
+    hipLaunchKernelGGL(k_kl_lp<T>, dim3(nct, (S + sg - 1) / sg), dim3(64 * LP_WAVES), lds, st, a, S, sg, nch);
+    return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
 }
 
 }  // namespace
+
+size_t kl_work_bytes(int S, int M, int prec) {
+    if (prec != FMGMC_KL_FP32 && prec != FMGMC_KL_BF16) return 0;
+    return size_t((S + 15) / 16) * lp_chunks(M, prec) * 64 * 16;
+}
 
 bool kl_separable(const KLArgs &a, int prec) {
     return prec == FMGMC_KL_FP64 && a.n >= SB && a.n % SB == 0 && a.kdim >= 1 && a.kdim <= 64;
@@ -374,9 +483,13 @@ int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st) {
     dim3 grid((a.n * a.n + TC - 1) / TC, (S + TS - 1) / TS), block(256);
     const size_t dyn = size_t(a.M) * (sizeof(double) + sizeof(int));
     if (prec == FMGMC_KL_FP64 || prec == FMGMC_KL_FP64_DENSE) hipLaunchKernelGGL(k_kl_f64, grid, block, dyn, st, a, S);
-    else if (prec == FMGMC_KL_FP32) hipLaunchKernelGGL(k_kl_f32, grid, block, dyn, st, a, S);
-    else if (prec == FMGMC_KL_BF16) hipLaunchKernelGGL(k_kl_bf16, grid, block, 0, st, a, S);
-    else {
+    else if (prec == FMGMC_KL_FP32 || prec == FMGMC_KL_BF16) {
+        if (!a.xw) {
+            set_error("launch_kl: the FP32 / BF16 contraction needs its xi workspace");
+            return FMGMC_EINVAL;
+        }
+        return prec == FMGMC_KL_FP32 ? launch_lp<float>(a, S, prec, st) : launch_lp<__bf16>(a, S, prec, st);
+    } else {
         set_error("launch_kl: unknown precision");
         return FMGMC_EINVAL;
     }

@@ -101,6 +101,83 @@ def test_field_reduced_precision_error(prec, bound):
     assert err.max() <= bound
 
 
+def _round_bf16(x):
+    """float64 -> bfloat16 in one rounding (to nearest, ties to even), as float64: the
+    52-bit significand is rounded to 7 bits in place (finite normal inputs)."""
+    u = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
+    one, sh = np.uint64(1), np.uint64(45)
+    u = ((u + ((one << np.uint64(44)) - one) + ((u >> sh) & one)) >> sh) << sh
+    return u.view(np.float64)
+
+
+def _kl_operand(cfg, n):
+    """B[m][j n + i] = sqrt(lambda_m) phi_{a_m}(i/n) phi_{b_m}(j/n) from the oracle's 1-D pieces."""
+    a, b, lam = table(cfg)
+    kd = int(max(a.max(), b.max())) + 1
+    w, _ = O.kl_1d(cfg["corr_len"], kd)
+    x = np.arange(n) / n
+    phi = np.array([O.kl_phi(k + 1, w[k], x) for k in range(kd)])
+    B = np.sqrt(lam)[:, None, None] * phi[a][:, None, :] * phi[b][:, :, None]
+    return B.reshape(len(a), n * n)
+
+
+@pytest.mark.parametrize("prec,M,n,S", [("bf16", 512, 64, 300), ("fp32", 512, 64, 300), ("bf16", 100, 32, 37),
+                                        ("fp32", 100, 32, 37), ("bf16", 64, 16, 5), ("fp32", 48, 16, 5),
+                                        ("bf16", 64, 256, 300), ("fp32", 64, 256, 300), ("bf16", 1100, 64, 20),
+                                        ("fp32", 600, 64, 20)])
+def test_field_reduced_precision_rounding(prec, M, n, S):
+    """The FP32 / BF16 contraction computes sum_m r(xi_m) r(B_m) with r the rounding of
+    each FP64 input to the input type (once, to nearest even), up to FP32
+    accumulation: |log K - g| <= M 2^-24 sum_m |r(xi_m) r(B_m)| + 1e-6 (exp and log).
+    Ragged sample counts (300 = a full and a partial 256-sample tile, two tiles in one
+    workgroup at 256^2), a mode count that is no multiple of 32, grids smaller than one
+    64-cell tile, and mode counts beyond what one workgroup keeps in LDS (BF16 > 1024,
+    FP32 > 512)."""
+    cfg = dict(sigma2=2.0, corr_len=0.1, n_modes=M, n_levels=1, n0=n)
+    xi = inputs.mc_normals(S, M, config=3, level=0, purpose=1)
+    log(f"field {prec} M {M} n {n} S {S}")
+    with fmgmc.Context(**cfg, kl_prec=prec) as ctx:
+        K = torch.zeros((S, n, n), dtype=torch.float64, device="cuda")
+        ctx.synthesize_field(0, dev(xi), K)
+        torch.cuda.synchronize()
+        g = np.log(K.cpu().numpy().reshape(S, n * n))
+    B = _kl_operand(cfg, n)
+    ref0 = O.field(n, cfg["corr_len"], table(cfg), xi[0]).reshape(-1)
+    assert np.max(np.abs(np.exp(xi[0] @ B) / ref0 - 1)) < 1e-12  # the operand above is the oracle's
+    if prec == "bf16":
+        xr, Br = _round_bf16(xi), _round_bf16(B)
+    else:
+        xr, Br = xi.astype(np.float32), B.astype(np.float32)
+    xr, Br = xr.astype(np.float64), Br.astype(np.float64)
+    gref = xr @ Br
+    tol = M * 2.0 ** -24 * (np.abs(xr) @ np.abs(Br)) + 1e-6
+    err = np.abs(g - gref)
+    log(f"  max |log K - g| {err.max():.2e} (max of err/tol {np.max(err / tol):.3f})")
+    assert np.all(err <= tol)
+
+
+def test_solve_reduced_precision_kl():
+    """Solves on an FP32 / BF16 field: the fine and coarse QoIs (the coarse one is read
+    on the first coarsened coefficient level the KL pass writes) stay within the field's
+    rounding of the oracle's, and the cycle counts match."""
+    cfg = dict(sigma2=1.0, corr_len=0.2, n_modes=256, n_levels=3, n0=32)
+    level, S = 2, 40
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=2)
+    of, oc, ocy, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], table(cfg), cfg["n0"] << level, level, xi,
+                                   nthreads=O.max_threads())
+    for solver in ("fp64", "fp32_ir"):
+        for prec, bound in (("fp32", 1e-4), ("bf16", 5e-2)):
+            with fmgmc.Context(**cfg, kl_prec=prec, solver=solver) as ctx:
+                rc, qf, qc, cyc, fl = run_level(ctx, level, xi)
+            assert rc == 0 and not fl.any()
+            ef, ec = np.max(np.abs(qf / of - 1)), np.max(np.abs(qc / oc - 1))
+            same = np.mean(np.all(cyc == ocy, axis=1))
+            log(f"  {solver} {prec}: Q^f rel err {ef:.2e}, Q^c rel err {ec:.2e}, same cycles {same:.2f}")
+            assert ef <= bound and ec <= bound
+            if solver == "fp64" and prec == "fp32":
+                assert same >= 0.9
+
+
 def test_context_mode_table():
     with fmgmc.Context(**CFG2) as ctx:
         a, b, lam = ctx.mode_table()
