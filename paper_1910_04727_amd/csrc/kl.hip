@@ -322,22 +322,27 @@ __device__ __forceinline__ void lp_mma(f4 (&acc)[2][4], const bf8 &a0, const bf8
     }
 }
 
-// epilogue for one (sample, cell): K = exp(g), the fine field streamed out (it is
-// read back only by later passes), the coarse levels by the cells with both
-// indices even
-__device__ __forceinline__ void lp_store(const KLArgs &A, int S, int s, int c, float g) {
-    const int n = A.n;
-    if (s >= S || c >= n * n) return;
-    const int i = c % n, j = c / n;
+// epilogue for one (sample, cell c of pyramid level k, an nk x nk plane): K = exp(g)
+// into the level's FP64 and FP32 planes
+__device__ __forceinline__ void lp_store(const KLArgs &A, int S, int k, int nk, int s, int c, float g) {
+    if (s >= S || c >= nk * nk) return;
     const float kf = __expf(g);
-    const double kv = double(kf);
-    const size_t o = size_t(s) * n * n + c;
-    if (A.K64[0]) __builtin_nontemporal_store(kv, A.K64[0] + o);
-    if (A.K32[0]) __builtin_nontemporal_store(kf, A.K32[0] + o);
-    if (!((i | j) & 1)) store_coarse(A, s, i, j, kv);
+    const size_t o = size_t(s) * nk * nk + c;
+    if (A.K64[k]) __builtin_nontemporal_store(double(kf), A.K64[k] + o);
+    if (A.K32[k]) __builtin_nontemporal_store(kf, A.K32[k] + o);
 }
 
-// Workgroup: cells c0 .. c0+63, samples [blockIdx.y sg, +sg) in tiles of LP_TILE.
+// 64-cell tiles of pyramid level k (cells of the nk x nk plane, nk = n / 2^k)
+__host__ __device__ __forceinline__ int lp_level_tiles(int n, int k) {
+    const int nk = n >> k;
+    return (nk * nk + 63) / 64;
+}
+
+// Workgroup: 64 consecutive cells c0 .. c0+63 of one pyramid level's plane, samples
+// [blockIdx.y sg, +sg) in tiles of LP_TILE. Every level is contracted for its own
+// cells (cell (I, J) of level k is the grid point (2^k I, 2^k J), so its column of
+// Phi, and with it every bit of g, is that of the fine cell it injects), which
+// makes every store of every level a run of contiguous cells.
 // The A slots of a wave stream through a ring of PF registers, PF slots ahead of
 // their use (three for BF16, whose K-step is a quarter of the FP32 one's
 // matrix-core time; one for FP32).
@@ -347,14 +352,16 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_kl_lp(KLArgs A, int S, int sg
     constexpr int CM = Lp<T>::CM, EPS = 16 / sizeof(T), PF = sizeof(T) == 2 ? 3 : 1;
     extern __shared__ __align__(16) unsigned char lp_lds[];
     V *Bs = reinterpret_cast<V *>(lp_lds);  // [slot][16-cell group q][lane]
-    const int n = A.n, nn = n * n, M = A.M;
-    const int c0 = blockIdx.x * 64, sb = blockIdx.y * sg, se = min(S, sb + sg);
+    const int n = A.n, M = A.M;
+    int lev = 0, tile = blockIdx.x;
+    while (lev + 1 < A.nlev && tile >= lp_level_tiles(n, lev)) tile -= lp_level_tiles(n, lev++);
+    const int nk = n >> lev, c0 = tile * 64, sb = blockIdx.y * sg, se = min(S, sb + sg);
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const V *X = static_cast<const V *>(A.xw);
     // slice builder: thread t fills the slots of cell group bq, lane l, every other slot
     const int bq = w & 3, bh = w >> 2, bc = c0 + 16 * bq + (l & 15);
-    const bool bval = bc < nn;
-    const int bi = bval ? bc % n : 0, bj = bval ? bc / n : 0;
+    const bool bval = bc < nk * nk;
+    const int bi = bval ? (bc % nk) << lev : 0, bj = bval ? (bc / nk) << lev : 0;
     auto build = [&](int kb0, int nb) {
         for (int k = bh; k < nb; k += 2) {
             V v;
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(64 * LP_WAVES) void k_kl_lp(KLArgs A, int S, int sg
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    lp_store(A, S, s0 + 16 * r + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), acc[r][q][v]);
+                    lp_store(A, S, lev, nk, s0 + 16 * r + 4 * (l >> 4) + v, c0 + 16 * q + (l & 15), acc[r][q][v]);
     }
 }
 
@@ -446,7 +453,9 @@ int launch_lp(const KLArgs &a, int S, int prec, hipStream_t st) {
                        static_cast<V *>(a.xw));
     // enough workgroups to fill the chip; each keeps its Phi slice for as many
     // sample tiles as that allows
-    const int nct = (a.n * a.n + 63) / 64, tiles = (S + LP_TILE - 1) / LP_TILE;
+    int nct = 0;
+    for (int k = 0; k < a.nlev; ++k) nct += lp_level_tiles(a.n, k);
+    const int tiles = (S + LP_TILE - 1) / LP_TILE;
     const int groups = std::max(1, std::min(tiles, (1024 + nct - 1) / nct));
     const int sg = (tiles + groups - 1) / groups * LP_TILE;
     hipLaunchKernelGGL(k_kl_lp<T>, dim3(nct, (S + sg - 1) / sg), dim3(64 * LP_WAVES), lds, st, a, S, sg, nch);
@@ -466,7 +475,11 @@ bool kl_separable(const KLArgs &a, int prec) {
 
 double kl_flops(const KLArgs &a, int prec) {
     const double n = a.n, kd = a.kdim;
-    return kl_separable(a, prec) ? 2.0 * kd * n * (kd + n) : 2.0 * double(a.M) * n * n;
+    if (kl_separable(a, prec)) return 2.0 * kd * n * (kd + n);
+    double cells = double(n) * n;  // the FP32 / BF16 contraction also computes the coarse levels' cells
+    if (prec == FMGMC_KL_FP32 || prec == FMGMC_KL_BF16)
+        for (int k = 1; k < a.nlev; ++k) cells += double(a.n >> k) * (a.n >> k);
+    return 2.0 * double(a.M) * cells;
 }
 
 int launch_kl(const KLArgs &a, int S, int prec, hipStream_t st) {
