@@ -535,7 +535,11 @@ int iterate_stage(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int k, int S
     while (true) {
         if (na > 0 && done < c->opts.max_cycles && inflight < ahead) {
             const int g = std::min(G, (c->opts.max_cycles - done + per_cycle - 1) / per_cycle);
-            const bool graph = tn.graphs && !prof;
+            // only full chunks are captured: a ragged chunk runs eagerly, so arbitrary
+            // sample counts (the adaptive drivers' increments) add no graphs and the
+            // cache holds at most one per (level, stage grid, block length)
+            const int full = (tn.batch > 0 && tn.batch < W.S_max) ? tn.batch : W.S_max;
+            const bool graph = tn.graphs && !prof && S == full;
             TRY(run_block(W, graph, std::make_tuple(level, k, g, S), st, [&]() -> int {
                 for (int i = 0; i < g; ++i) TRY(cycle_and_check());
                 return FMGMC_OK;

@@ -98,8 +98,9 @@ def test_graph_replay_matches_eager(solver, level):
 
     Several calls replay the captured blocks, with unrelated eager GPU work and
     synchronisations between them; every replay must equal the eager result.
-    The batch (5) is below the sample count (13), so chunks replay the graphs
-    too, the last one with its own (ragged) batch size.
+    The batch (5) is below the sample count (13): the two full chunks replay
+    the graphs, the ragged last one (3 samples) runs eagerly, as every chunk
+    smaller than the batch does (so arbitrary sample counts add no graphs).
     """
     S = 13
     xi = torch.from_numpy(inputs.mc_normals(S, CFG2["n_modes"], config=2, level=level, purpose=3)).to("cuda")
@@ -120,10 +121,11 @@ def test_graph_replay_matches_eager(solver, level):
 
 
 def test_graph_replay_on_user_stream():
-    """Per-level solve on a caller's non-default stream with graphs on."""
+    """Per-level solve on a caller's non-default stream with graphs on (the batch
+    equals the sample count, so the one chunk is a full one and is captured)."""
     level, S = 2, 9
     xi = torch.from_numpy(inputs.mc_normals(S, CFG2["n_modes"], config=2, level=level, purpose=3)).to("cuda")
-    with fmgmc.Context(**CFG2, solver="fp32_ir") as ctx:
+    with fmgmc.Context(**CFG2, solver="fp32_ir", max_batch=S) as ctx:
         eager = solve(ctx, level, xi)
         ctx.set_schedule(level, check_every=2, graphs=1, batch=0)
         s = torch.cuda.Stream()
