@@ -6,8 +6,9 @@
 // of columns 2l and 2l+1 of every row, one red and one black, so every lane
 // updates exactly one cell in every half-sweep. The workgroup marches up the
 // rows. At step F it takes row F (loaded NH+1 steps earlier into a register
-// queue, so HBM latency overlaps the work of NH+1 rows) and applies half-sweep
-// t (t = 1..NH, red first) to row F - t: this is the wavefront order of the
+// queue, three in the FP32 passes of eight half-sweeps, so HBM latency
+// overlaps the work of that many rows) and applies half-sweep t (t = 1..NH,
+// red first) to row F - t: this is the wavefront order of the
 // sweeps, so the result is exactly that of NH sequential half-sweeps. The
 // residual follows at row F - NH - 1 and is summed over 2x2 blocks into the
 // next coarser grid and/or squared into the sample's residual norm. Every
@@ -96,9 +97,12 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     constexpr int U = NH + 1;    // register ring depth = unroll
     constexpr int RX = march_ring_rows(NH);  // LDS x ring rows (>= NH + 3), power of two
     // prefetch distance of the load queue (a divisor of U, so that a row's queue
-    // slot is a constant after unrolling). Measured: three rows instead of nine
-    // in the eight-half-sweep pass frees 42 VGPRs but runs 2% slower.
-    constexpr int D = U;
+    // slot is a constant after unrolling, and row F + D lands in the slot that
+    // step F + D reads): U rows, or three in the FP32 passes of eight
+    // half-sweeps, whose registers then fit three waves per SIMD (see RC
+    // below); the eight-half-sweep pass measured 7% faster so.
+    constexpr int D = (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3 : U;
+    static_assert(U % D == 0, "the load queue depth must divide the unroll");
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
     constexpr bool LX = (INIT == INIT_LOAD || INIT == INIT_PROLONG);
@@ -162,17 +166,18 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     V2<T> bprev{T(0), T(0)}, bcur{T(0), T(0)};
     T eprev = T(0), ecur = T(0);                 // east boundary face of rows F-1, F (correction)
     T rprev = T(0), rr = T(0), q = T(0);
-    // FP32: this lane's cell pairs of the rows in flight (hv[t], the row that
-    // half-sweep t acted on last; hv[0], the row that entered last; hres, the
-    // row below the residual's row), so that the sweeps read only the west /
-    // east neighbours from LDS. FP64 reads them from the LDS ring (its
-    // register rings leave no room).
-    constexpr bool RC = sizeof(T) == 4;
-    // FP64: 1/diagonal recomputed in each half-sweep from the coefficient ring
-    // instead of being held in a ring of its own; the registers this frees keep
-    // the FP64 correction passes from spilling (the sum now starts from the
-    // faces as stored, so results move at the rounding level)
-    constexpr bool RI = sizeof(T) == 8;
+    // FP32 passes of up to four half-sweeps: this lane's cell pairs of the rows
+    // in flight (hv[t], the row that half-sweep t acted on last; hv[0], the row
+    // that entered last; hres, the row below the residual's row), so that the
+    // sweeps read only the west / east neighbours from LDS. FP64, and the FP32
+    // passes of six and eight half-sweeps, read them from the LDS ring: their
+    // register rings leave no room (the eight-half-sweep pass drops from 252
+    // VGPRs, two waves per SIMD, to 162, three).
+    constexpr bool RC = sizeof(T) == 4 && NH < 6;
+    // FP64 and the long FP32 passes: 1/diagonal recomputed in each half-sweep
+    // from the coefficient ring instead of being held in a ring of its own; the
+    // registers this frees keep the FP64 correction passes from spilling
+    constexpr bool RI = sizeof(T) == 8 || NH >= 6;
     V2<T> hv[NH + 1];
 #pragma unroll
     for (int t = 0; t <= NH; ++t) hv[t] = V2<T>{T(0), T(0)};
