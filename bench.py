@@ -644,7 +644,8 @@ def report_cfg4(torch, fmgmc, inputs, args):
     L = len(ns)
     xd = [_dev(torch, inputs.mc_normals_blocked(0, n, cfg["n_modes"], config=4, level=l)) for l, n in enumerate(ns)]
     out = [_bufs(torch, n) for n in ns]
-    res = {}
+    # concurrent levels run on one lane (host thread + stream) per hardware queue
+    res = {"hardware_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))}
     with fmgmc.Context(**cfg, solver="fp32_ir", max_batch=512, max_cycles=60) as ctx:
         def seq():
             for l in range(L):

@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <functional>
@@ -49,7 +50,7 @@ namespace {
 
 constexpr int kMaxGrid = 9;    // grid indices: n_coarsest << k
 constexpr int kSmallTop = 32;  // grids up to this size run whole cycles in LDS
-constexpr int kMaxLanes = 4;   // concurrent levels in fmgmc_solve_levels (one hardware queue each)
+constexpr int kMaxLanes = 16;  // most concurrent levels in fmgmc_solve_levels (one hardware queue each)
 
 int ilog2(int v) {
     int r = 0;
@@ -1206,7 +1207,7 @@ int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples, 
     std::vector<int> rcs(n_lev, FMGMC_OK);
     std::vector<std::string> msgs(n_lev);
     std::vector<char> ncs(n_lev, 0), nfs(n_lev, 0);
-    // Lanes: at most kMaxLanes host threads, each with one stream, so that every
+    // Lanes: one host thread with one stream per hardware queue, so that every
     // lane keeps a hardware queue of its own (the runtime maps streams onto a
     // few hardware queues; two levels sharing one would interleave their many
     // launches in order). Levels go to lanes longest first, each to the lane
@@ -1221,7 +1222,10 @@ int fmgmc_solve_levels(fmgmc_ctx *ctx, int32_t n_lev, const int64_t *n_samples, 
         return double(n_samples[l]) * std::max(n * n, 4096.0);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    const int nl = std::min<int>(int(order.size()), kMaxLanes);
+    // as many lanes as the runtime has hardware queues (GPU_MAX_HW_QUEUES, 4 by default)
+    int hwq = 4;
+    if (const char *e = std::getenv("GPU_MAX_HW_QUEUES")) hwq = std::max(1, std::atoi(e));
+    const int nl = std::min({int(order.size()), hwq, kMaxLanes});
     while (int(ctx->lanes.size()) < nl) {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
