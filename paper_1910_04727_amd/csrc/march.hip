@@ -166,14 +166,17 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     V2<T> bprev{T(0), T(0)}, bcur{T(0), T(0)};
     T eprev = T(0), ecur = T(0);                 // east boundary face of rows F-1, F (correction)
     T rprev = T(0), rr = T(0), q = T(0);
-    // FP32 passes of up to four half-sweeps: this lane's cell pairs of the rows
-    // in flight (hv[t], the row that half-sweep t acted on last; hv[0], the row
-    // that entered last; hres, the row below the residual's row), so that the
-    // sweeps read only the west / east neighbours from LDS. FP64, and the FP32
-    // passes of six and eight half-sweeps, read them from the LDS ring: their
-    // register rings leave no room (the eight-half-sweep pass drops from 252
-    // VGPRs, two waves per SIMD, to 162, three).
-    constexpr bool RC = sizeof(T) == 4 && NH < 6;
+    // FP32 passes of up to four half-sweeps, and the FP64 stage-operator passes
+    // with boundary-data right-hand sides: this lane's cell pairs of the rows in
+    // flight (hv[t], the row that half-sweep t acted on last; hv[0], the row that
+    // entered last; hres, the row below the residual's row), so that the sweeps
+    // read only the west / east neighbours from LDS. In FP64 that halves the LDS
+    // traffic that bounds these passes (two waves per SIMD either way: 206
+    // VGPRs, and 58 KB of LDS at 512^2). The other passes read them from the LDS
+    // ring: their register rings leave no room (the FP32 eight-half-sweep pass
+    // drops from 252 VGPRs, two waves per SIMD, to 162, three; the FP64
+    // correction passes would spill).
+    constexpr bool RC = (sizeof(T) == 4 && NH < 6) || (sizeof(T) == 8 && CK && !RHSA);
     // FP64 and the long FP32 passes: 1/diagonal recomputed in each half-sweep
     // from the coefficient ring instead of being held in a ring of its own; the
     // registers this frees keep the FP64 correction passes from spilling
