@@ -151,25 +151,17 @@ __global__ __launch_bounds__(256) void k_kl_f64(KLArgs A, int S) {
 // L2-resident [kdim][n] table; no two waves load the same operand, and no
 // barrier separates the tiles. LDS holds only C_s, then T
 // (the same space, 80-double rows, conflict-free operand reads): 30 KB at 48
-// modes per axis. The epilogue (exp, the pyramid) writes 16 values per lane
-// per tile; the parity of a lane's rows and columns is fixed, so the coarse
-// levels are taken only by the lanes that own even cells.
+// modes per axis. The epilogue (exp) writes 16 fine values per lane per tile.
+// The coarse levels of the pyramid: the four waves take their tiles in rounds
+// of 64 adjacent columns; a round's level-1 cells (even row, even column: 32
+// x 32 of them) are staged in LDS, and after the round's barrier the workgroup
+// stores them as whole rows, 32 adjacent coarse cells per row and store
+// instruction, and the deeper levels from the same block. (Stored from the
+// lanes that own them, they were short partial-line runs over every level,
+// which cost as much as the fine field's own stores.)
 constexpr int SB = 64;
 constexpr int TSTR = SB + 16;
-
-// levels >= 1 of the pyramid for one fine cell (i, j) with both indices even
-__device__ __forceinline__ void store_coarse(const KLArgs &A, int s, int i, int j, double kv) {
-    int nl = A.n, ii = i, jj = j;
-    for (int k = 1; k < A.nlev; ++k) {
-        ii >>= 1;
-        jj >>= 1;
-        nl >>= 1;
-        const size_t o = size_t(s) * nl * nl + size_t(jj) * nl + ii;
-        if (A.K64[k]) A.K64[k][o] = kv;
-        if (A.K32[k]) A.K32[k][o] = float(kv);
-        if ((ii & 1) || (jj & 1)) break;
-    }
-}
+constexpr int L1S = 33;  // row stride (doubles) of the staged 32 x 32 level-1 block
 
 template <int AP>
 __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
@@ -179,6 +171,7 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
     extern __shared__ double sm[];
     double *Cm = sm;                 // [AP][CSd]   C_s[a][b]
     double *Tt = sm;                 // [AP][TSTR]  T_s[a][j] of the band (replaces C_s)
+    double *L1 = sm + AP * TSTR;     // [32][L1S]   level-1 cells of one round of tiles
     const int n = A.n, s = blockIdx.y, j0 = blockIdx.x * SB, KD = A.kdim;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     if (s >= S) return;
@@ -211,11 +204,14 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
     // lane l holds output rows 4v + l/16 (+16g) and column l%16 of a tile
     const int r0 = l >> 4, c0 = l & 15;
     const bool even = ((r0 | c0) & 1) == 0;
-    for (int i0 = 16 * w; i0 < n; i0 += 64) {
+    const bool pyr = A.nlev > 1;
+    for (int i0 = 16 * w; i0 < n; i0 += 64) {  // the same trip count in every wave
         d4 acc[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) acc[g] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+        // (unrolled by three: by four the level-1 staging pushes the kernel past 128
+        // registers, three waves per SIMD instead of four)
+#pragma unroll 3
         for (int kk = 0; kk < KK; ++kk) {
             const double bv = phi(4 * kk + r0, i0 + c0);
 #pragma unroll
@@ -235,15 +231,38 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
                 // the fine field streams out (read back only by later passes)
                 if (A.K64[0]) __builtin_nontemporal_store(kv, A.K64[0] + o);
                 if (A.K32[0]) __builtin_nontemporal_store(float(kv), A.K32[0] + o);
-                if (even) store_coarse(A, s, i, j, kv);
+                // level-1 cell (row 8g + 2v + r0/2, column 8w + c0/2 of the round's block)
+                if (pyr && even) L1[(8 * g + 2 * v + (r0 >> 1)) * L1S + 8 * w + (c0 >> 1)] = kv;
             }
         }
+        if (!pyr) continue;
+        __syncthreads();
+        // the round's block: level-1 rows J1 = j0/2 + Jb, columns I1 = 32 rnd + Ib; level k
+        // takes the cells of level k - 1 with both indices even
+        const int J1b = j0 >> 1, I1b = (i0 - 16 * w) >> 1;
+#pragma unroll 1
+        for (int e = t; e < 32 * 32; e += 256) {
+            const int Jb = e >> 5, Ib = e & 31, J1 = J1b + Jb, I1 = I1b + Ib;
+            const double kv = L1[Jb * L1S + Ib];
+            int nl = n >> 1, jj = J1, ii = I1;
+            for (int k = 1; k < A.nlev; ++k) {
+                const size_t o = size_t(s) * nl * nl + size_t(jj) * nl + ii;
+                if (A.K64[k]) A.K64[k][o] = kv;
+                if (A.K32[k]) A.K32[k][o] = float(kv);
+                if ((ii | jj) & 1) break;
+                ii >>= 1;
+                jj >>= 1;
+                nl >>= 1;
+            }
+        }
+        __syncthreads();
     }
 }
 
 template <int AP>
 size_t sep_lds() {
-    return size_t(AP) * TSTR * sizeof(double);  // C_s ([AP][AP+2]) and T ([AP][TSTR]) share it
+    // C_s ([AP][AP+2]) and T ([AP][TSTR]) share the first part; then the level-1 block
+    return (size_t(AP) * TSTR + 32 * L1S) * sizeof(double);
 }
 
 // ------------------------------------------------------ dense, FP32 / BF16 inputs
