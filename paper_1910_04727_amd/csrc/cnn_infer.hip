@@ -29,6 +29,16 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int CH = kCnnWidth;   // 32 channels
 constexpr int CS = 40;          // LDS cell stride in bf16 (80 bytes)
+// Storage order of a cell's 32 channels (in HBM and in LDS): position
+// 8 g + 4 q + v holds channel 16 q + 4 g + v (g < 4, q < 2, v < 4). In the
+// fused kernel's D layout lane l holds channels 16 q + 4 (l / 16) + v of a
+// cell, so its eight values are one 16-byte word and its epilogue stores and
+// residual reads are single 16-byte accesses (conflict-free at the 80-byte
+// cell stride; 8-byte ones two-way conflicted). The input-channel order of
+// the packed weights follows, so every contraction runs over the positions.
+__host__ __device__ constexpr int cnn_pos(int c) { return 8 * ((c >> 2) & 3) + 4 * (c >> 4) + (c & 3); }
+__host__ __device__ constexpr int cnn_chan(int p) { return 16 * ((p >> 2) & 1) + 4 * (p >> 3) + (p & 3); }
+static_assert(cnn_chan(cnn_pos(21)) == 21 && cnn_pos(cnn_chan(13)) == 13, "channel order");
 constexpr int ROWS = 4;         // output rows per workgroup (one per wave)
 constexpr int IR = ROWS + 2;    // staged input rows
 
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(256) void k_cnn_layer(LayerArgs A) {
                 z = z > 0.f ? z : 0.f;
                 if (KIND == L_MID) {
                     const int c = 16 * m + 4 * (l >> 4) + v;
-                    z += float(tile[((w + 1) * (TW + 2) + c + 1) * CS + co]);
+                    z += float(tile[((w + 1) * (TW + 2) + c + 1) * CS + cnn_pos(co)]);
                 }
                 res[m][q][v] = z;
             }
@@ -184,7 +194,7 @@ __global__ __launch_bounds__(256) void k_cnn_layer(LayerArgs A) {
         for (int q = 0; q < NT; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                tile[(w * TW + 16 * m + 4 * (l >> 4) + v) * CH + 16 * q + (l & 15)] = __bf16(res[m][q][v]);
+                tile[(w * TW + 16 * m + 4 * (l >> 4) + v) * CH + cnn_pos(16 * q + (l & 15))] = __bf16(res[m][q][v]);
     __syncthreads();
     __bf16 *dst = A.out + size_t(sl) * nn * CH;
     for (int e = t; e < ROWS * TW * 4; e += 256) {
@@ -287,7 +297,6 @@ __global__ __launch_bounds__(512) void k_cnn_fused(FusedArgs A) {
             bz[q][v] = A.bias[0][16 * q + 4 * (l >> 4) + v];
             ba[q][v] = A.bias[la][16 * q + 4 * (l >> 4) + v];
         }
-    typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
     // hidden layer k on row r (cell tiles 2 half, 2 half + 1) from ring k - 1 into
     // ring k (k >= 1), or layer 0 from the input planes
     auto hidden = [&](int k, int r, const bf8 *wk, const float (*bk)[4]) {
@@ -330,27 +339,27 @@ __global__ __launch_bounds__(512) void k_cnn_fused(FusedArgs A) {
                 }
             }
         }
-        // epilogue: bias, ReLU, the residual (k >= 1), zeros outside the domain
+        // epilogue: bias, ReLU, the residual (k >= 1), zeros outside the domain; the
+        // lane's channels 16 q + 4 (l / 16) + v sit at positions 8 (l / 16) + 4 q + v
         const __bf16 *res = ring + (k > 0 ? k - 1 : 0) * FRING + (r & 3) * FROW;
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int c = 16 * (2 * half + m) + (l & 15), gc = gx0 + c;
             const bool in = gc >= 0 && gc < n;
+            const int pos = (c + 1) * CS + 8 * (l >> 4);
+            bf8 rv = bf8{};
+            if (k > 0) rv = *reinterpret_cast<const bf8 *>(res + pos);
+            bf8 out;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int ch = 16 * q + 4 * (l >> 4);
-                bf4 rv = bf4{};
-                if (k > 0) rv = *reinterpret_cast<const bf4 *>(res + (c + 1) * CS + ch);
-                bf4 out;
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     float z = acc[q][m][v] + bk[q][v];
                     z = z > 0.f ? z : 0.f;
-                    if (k > 0) z += float(rv[v]);
-                    out[v] = __bf16(in ? z : 0.f);
+                    if (k > 0) z += float(rv[4 * q + v]);
+                    out[4 * q + v] = __bf16(in ? z : 0.f);
                 }
-                *reinterpret_cast<bf4 *>(dst + (c + 1) * CS + ch) = out;
-            }
+            *reinterpret_cast<bf8 *>(dst + pos) = out;
         }
     };
     // output layer on row r for cell tile m (one channel tile; channel 0 is the output,
@@ -416,7 +425,7 @@ __global__ void k_pack_mid(const float *W, bf8 *frag, int nt) {
     const int tap = f / nt, q = f % nt, co = 16 * q + (l & 15);
     bf8 v;
     for (int e = 0; e < 8; ++e) {
-        const int ci = 8 * (l >> 4) + e;
+        const int ci = cnn_chan(8 * (l >> 4) + e);  // the input channel at that storage position
         float x = 0.f;
         if (nt == 2 || co == 0) x = W[(co * CH + ci) * 9 + tap];
         v[e] = __bf16(x);
