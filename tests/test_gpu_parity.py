@@ -156,6 +156,28 @@ def test_field_reduced_precision_rounding(prec, M, n, S):
     assert np.all(err <= tol)
 
 
+@pytest.mark.parametrize("prec,level", [("fp64", 2), ("fp64_dense", 2), ("fp32", 2), ("bf16", 2), ("bf16", 4),
+                                        ("fp32", 1)])
+def test_field_injection_is_the_coarse_field(prec, level):
+    """Cell (I, J) of the grid n/2 is the grid point (2I, 2J) of the grid n (R1, Section 2.5
+    coarsening): the field synthesized directly on n/2 equals the fine field at even cells
+    bit for bit, for every KL path (the FP32 / BF16 contraction computes each pyramid level
+    on its own tiles, so this also holds its coarse levels to the fine values they inject)."""
+    cfg = CFG2
+    n = cfg["n0"] << level
+    S = 37
+    xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=1)
+    log(f"injection {prec} n {n} S {S}")
+    with fmgmc.Context(**cfg, kl_prec=prec) as ctx:
+        Kf = torch.zeros((S, n, n), dtype=torch.float64, device="cuda")
+        Kc = torch.zeros((S, n // 2, n // 2), dtype=torch.float64, device="cuda")
+        ctx.synthesize_field(level, dev(xi), Kf)
+        ctx.synthesize_field(level - 1, dev(xi), Kc)
+        torch.cuda.synchronize()
+    Kf, Kc = Kf.cpu().numpy(), Kc.cpu().numpy()
+    assert np.array_equal(Kf[:, ::2, ::2], Kc)
+
+
 def test_solve_reduced_precision_kl():
     """Solves on an FP32 / BF16 field: the fine and coarse QoIs (the coarse one is read
     on the first coarsened coefficient level the KL pass writes) stay within the field's
