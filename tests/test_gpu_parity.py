@@ -124,7 +124,7 @@ def _kl_operand(cfg, n):
 @pytest.mark.parametrize("prec,M,n,S", [("bf16", 512, 64, 300), ("fp32", 512, 64, 300), ("bf16", 100, 32, 37),
                                         ("fp32", 100, 32, 37), ("bf16", 64, 16, 5), ("fp32", 48, 16, 5),
                                         ("bf16", 64, 256, 300), ("fp32", 64, 256, 300), ("bf16", 1100, 64, 20),
-                                        ("fp32", 600, 64, 20)])
+                                        ("fp32", 600, 64, 20), ("bf16", 4096, 32, 9), ("fp32", 4096, 32, 9)])
 def test_field_reduced_precision_rounding(prec, M, n, S):
     """The FP32 / BF16 contraction computes sum_m r(xi_m) r(B_m) with r the rounding of
     each FP64 input to the input type (once, to nearest even), up to FP32
@@ -132,7 +132,7 @@ def test_field_reduced_precision_rounding(prec, M, n, S):
     Ragged sample counts (300 = a full and a partial 256-sample tile, two tiles in one
     workgroup at 256^2), a mode count that is no multiple of 32, grids smaller than one
     64-cell tile, and mode counts beyond what one workgroup keeps in LDS (BF16 > 1024,
-    FP32 > 512)."""
+    FP32 > 512), up to the largest mode count the library takes (4096)."""
     cfg = dict(sigma2=2.0, corr_len=0.1, n_modes=M, n_levels=1, n0=n)
     xi = inputs.mc_normals(S, M, config=3, level=0, purpose=1)
     log(f"field {prec} M {M} n {n} S {S}")
