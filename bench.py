@@ -770,7 +770,7 @@ def report_saving(torch, fmgmc, inputs, args):
     cfg = dict(CFG)
     S = args.samples
     res = []
-    # "tolerance": both QoI stages driven to rel-res 1e-10 (this build's stopping rule);
+    # "tolerance": both QoI stages driven to rel-res 1e-10 (the library's stopping rule);
     # "one_cycle": every FMG stage gets one V-cycle (the paper's reading that FMG stage
     # ends are exact), FP64 only
     for form, rule in (("fp32_ir", "tolerance"), ("fp64", "tolerance"), ("fp64", "one_cycle")):
