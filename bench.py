@@ -101,7 +101,7 @@ def run_form(torch, fmgmc, xi_dev, form, args, tol=None, steps=None, warmup=None
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
 # (profiles/hbm_traffic_512.md; taken offline, not in this run). None once a
 # kernel changes after measurement.
-TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000, "fused": 1.000}
+TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000, "fused": 1.000, "irpre": None}
 TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE passes over the same launch, calibrated on a plain "
                   "copy (profiles/hbm_traffic_512.md); taken offline, not in this run")
 STENCIL_TARGET = 0.60  # fraction of the HBM peak the stencil passes aim for
@@ -110,7 +110,7 @@ STENCIL_TARGET = 0.60  # fraction of the HBM peak the stencil passes aim for
 def roofline(form, steps):
     """Dominant HBM-bound kernel of a form from the library's event timing."""
     best = None
-    for kind in ("pre", "post", "ir", "fused"):
+    for kind in ("pre", "post", "ir", "fused", "irpre"):
         ms, n, alg = form["prof"][kind]
         if n and (best is None or ms > best[1]):
             best = (kind, ms, n, alg)
@@ -132,7 +132,7 @@ def pass_table(form):
     """Per-kind figures of the three timed 512^2 stage passes: launches, mean
     launch time and algorithmic GB/s (the roofline picks the largest total)."""
     out = {}
-    for kind in ("pre", "post", "ir", "fused"):
+    for kind in ("pre", "post", "ir", "fused", "irpre"):
         ms, n, alg = form["prof"][kind]
         if n:
             gbs = alg / (ms * 1e-3) / 1e9

@@ -119,9 +119,12 @@ typedef struct {
                               refinement between them, the post-smoothing pass of one cycle and
                               the pre-smoothing pass of the next run as one pass over the stage
                               grid (the same sweeps in the same order, with x, K and b read
-                              once instead of twice); needs nu1 + nu2 <= 4. 0 = separate
-                              passes. Converged results agree to the stopping tolerance; the
-                              FP32 iterates may differ in rounding. */
+                              once instead of twice); needs nu1 + nu2 <= 4. With nu1 <= 2,
+                              each FP64 refinement pass also does the pre-smoothing and
+                              restriction of the FP32 cycle after it (its residual is that
+                              cycle's right-hand side). 0 = separate passes. Converged
+                              results agree to the stopping tolerance; the FP32 iterates may
+                              differ in rounding. */
     int32_t warm;          /* FMGMC_WARM_NONE, or FMGMC_WARM_CNN: fmgmc_create loads the network
                               file cnn_weights into a network the context owns and warm-starts
                               every QoI stage with n >= warm_min_n from it (as
@@ -307,13 +310,15 @@ int fmgmc_kl_modes(double sigma2, double corr_len, int32_t n_modes, int32_t *a, 
  * axis), 4 coarse-grid V-cycle in LDS, 5 warm-start network
  * inference (flops; all its layers, every QoI stage it runs on), 6 fused
  * prolongation + post-smoothing + pre-smoothing + residual + restriction pass
- * (fuse_cycles).
+ * (fuse_cycles), 7 FP64 refinement pass that also does the next FP32 cycle's
+ * pre-smoothing + residual + restriction (fuse_cycles).
  * fmgmc_profile_read synchronises, returns the summed kernel time in ms,
  * the launch count and the algorithmic bytes (flops for kind 3), and clears
  * the kind's record.
  */
 enum { FMGMC_PROF_PRE = 0, FMGMC_PROF_POST = 1, FMGMC_PROF_IR = 2, FMGMC_PROF_KL = 3,
-       FMGMC_PROF_SMALL = 4, FMGMC_PROF_CNN = 5, FMGMC_PROF_FUSED = 6, FMGMC_PROF_KINDS = 7 };
+       FMGMC_PROF_SMALL = 4, FMGMC_PROF_CNN = 5, FMGMC_PROF_FUSED = 6, FMGMC_PROF_IRPRE = 7,
+       FMGMC_PROF_KINDS = 8 };
 int fmgmc_profile_enable(fmgmc_ctx *ctx, int32_t enable);
 int fmgmc_profile_read(fmgmc_ctx *ctx, int32_t kind, double *ms, int64_t *launches, double *alg);
 

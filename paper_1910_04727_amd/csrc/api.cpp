@@ -620,8 +620,8 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
 // Learned warm start of one QoI stage (p64 holds the FMG start p~, rr its
 // residual norm, r32 its residual): p~ + rms(r) y, then the plain start is
 // restored for every sample whose residual did not drop.
-template <typename F>
-int warm_start(fmgmc_ctx *c, Work &W, int k, int S, const IRArgs &ia, hipStream_t st, F &&interp) {
+template <typename F, typename R>
+int warm_start(fmgmc_ctx *c, Work &W, int k, int S, const IRArgs &ia, hipStream_t st, F &&interp, R &&refine) {
     const int n = W.nsz[k];
     InferArgs a{};
     a.n = n;
@@ -641,10 +641,10 @@ int warm_start(fmgmc_ctx *c, Work &W, int k, int S, const IRArgs &ia, hipStream_
     // p += rms(r) y in FP64 and the residual of the corrected start, in one refinement pass
     IRArgs iw = ia;
     iw.e = W.x32[k];
-    TRY(launch_ir(iw, S, st));
+    TRY(refine(iw));
     TRY(launch_judge(S, W.rr, W.rr0, W.active, W.flags, st));  // active <- samples to restore
     TRY(interp());
-    TRY(launch_ir(ia, S, st));
+    TRY(refine(ia));
     return launch_fill_i32(W.active, 1, S, st);
 }
 
@@ -686,35 +686,69 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             ia.q = W.q;
             ia.active = W.active;
             ia.g = g;
-            {
-                // first residual of the stage: reads p and K, writes r (20 B per cell)
+            // back-to-back cycles on a marching top grid share their joining pass
+            const bool fuse = c->opts.fuse_cycles && k > c->small_top && c->opts.nu1 + c->opts.nu2 <= 4;
+            // ... and every refinement also does the pre-smoothing and restriction of
+            // the FP32 cycle after it (which then skips its own): the refinement's
+            // residual is that cycle's right-hand side, and its coefficients are
+            // float(K64), the stage's FP32 K
+            const bool fuse_ir = fuse && c->opts.nu1 <= 2;
+            // refinement pass: p (+= e), r = b - A p in FP64, r -> FP32, ||r||^2, Q
+            auto refine = [&](const IRArgs &a) -> int {
+                const double cells = double(W.n_active_host) * double(n) * n;
+                if (!fuse_ir) {
+                    // reads p, e and K, writes p and r (without e: reads p and K, writes r)
+                    const double b = cells * (a.e ? 8.0 + 4.0 + 8.0 + 8.0 + 4.0 : 8.0 + 8.0 + 4.0);
+                    if (k == W.top_grid) return timed(c, W, FMGMC_PROF_IR, b, st, [&] { return launch_ir(a, S, st); });
+                    return launch_ir(a, S, st);
+                }
+                MarchArgs<float> m{};
+                m.n = n;
+                m.x = W.x32[k];
+                m.bc = W.b32[k - 1];
+                m.rr = a.rr;
+                m.q = a.q;
+                m.active = a.active;
+                m.g = a.g;
+                m.p = a.p;
+                m.e = a.e;
+                m.K64 = a.K;
+                m.r32 = a.r32;
+                const int out = OUT_RESTRICT | (a.e ? OUT_PUPD : 0);
+                // the refinement's bytes, then x and the restricted residual out
+                const double b = cells * ((a.e ? 8.0 + 4.0 + 8.0 + 8.0 + 4.0 : 8.0 + 8.0 + 4.0) + 4.0 + 1.0);
+                auto go = [&] { return launch_march(m, S, 2 * c->opts.nu1, true, INIT_IR, true, out, st); };
+                if (k == W.top_grid) return timed(c, W, FMGMC_PROF_IRPRE, b, st, go);
+                return go();
+            };
+            const bool warm = c->warm && n >= c->warm_min_n && (c->warm_max_n == 0 || n <= c->warm_max_n);
+            // first residual of the stage (with the warm start, the network's input:
+            // a plain refinement pass, the warm start's own passes then do the rest)
+            if (warm && fuse_ir) {
                 const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
                 if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
                 else TRY(launch_ir(ia, S, st));
+            } else {
+                TRY(refine(ia));
             }
-            const bool warm = c->warm && n >= c->warm_min_n && (c->warm_max_n == 0 || n <= c->warm_max_n);
             float *capx = W.cap_x[slot], *capt = W.cap_t[slot];
             if (warm || capx) TRY(launch_copy_f64(W.rr, W.rr0, S, st));
             if (capx) {
                 TRY(launch_pack_x(n, S, W.K32[k], W.b32[k], W.rr0, capx, st));
                 TRY(launch_copy_f64(W.p64[k], W.p0, int64_t(S) * n * n, st));
             }
-            if (warm) TRY(warm_start(c, W, k, S, ia, st, interp));
+            if (warm) TRY(warm_start(c, W, k, S, ia, st, interp, refine));
             // FP32 cycles before the first FP64 refinement, and per refinement after it
             const int inner = std::max(1, c->opts.inner_cycles);
             const int first = std::min(c->opts.inner_first > 0 ? c->opts.inner_first : inner, c->opts.max_cycles);
-            // back-to-back cycles on a marching top grid share their joining pass
-            const bool fuse = c->opts.fuse_cycles && k > c->small_top && c->opts.nu1 + c->opts.nu2 <= 4;
             auto step = [&](int ni) -> int {
                 for (int ic = 0; ic < ni; ++ic) {
-                    const int flow = fuse ? ((ic > 0 ? VC_SKIP_PRE : 0) | (ic + 1 < ni ? VC_FUSE_POST : 0)) : 0;
+                    const int flow = fuse ? (((ic > 0 || fuse_ir) ? VC_SKIP_PRE : 0) | (ic + 1 < ni ? VC_FUSE_POST : 0)) : 0;
                     TRY(vcycle<float>(c, W, B, S, k, q, ic == 0 ? INIT_ZERO : INIT_LOAD, true, 0, st, flow));
                 }
                 IRArgs iu = ia;
                 iu.e = W.x32[k];
-                const double irb = double(W.n_active_host) * double(n) * n * (8.0 + 4.0 + 8.0 + 8.0 + 4.0);
-                if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb, st, [&] { return launch_ir(iu, S, st); }));
-                else TRY(launch_ir(iu, S, st));
+                TRY(refine(iu));
                 return launch_checks(c, W, S, slot, qout, ni, tol, st);
             };
             TRY(step(first));

@@ -64,8 +64,11 @@ struct Faces {
 };
 
 // march kernels: one workgroup per sample marching over the rows
-enum { INIT_ZERO = 0, INIT_LOAD = 1, INIT_PROLONG = 2, INIT_INTERP = 3 };
-enum { OUT_RESTRICT = 1, OUT_RR = 2, OUT_Q = 4 };
+// INIT_IR (FP32, stage operator): zero start; the right-hand side of each row
+// is the FP64 refinement residual of the stage iterate p, formed in the same
+// pass (with OUT_PUPD, p += e first and p written back), and K = float(K64).
+enum { INIT_ZERO = 0, INIT_LOAD = 1, INIT_PROLONG = 2, INIT_INTERP = 3, INIT_IR = 4 };
+enum { OUT_RESTRICT = 1, OUT_RR = 2, OUT_Q = 4, OUT_PUPD = 8 };
 
 template <typename T>
 struct MarchArgs {
@@ -80,6 +83,12 @@ struct MarchArgs {
     double *q;            // [S] QoI (OUT_Q)
     const int32_t *active;// [S] nonzero = sample still iterating
     Bnd g;
+    // INIT_IR only: the refinement's operands (rr and q then take its FP64
+    // residual norm and QoI)
+    double *p;            // [S][n][n] FP64 stage iterate
+    const float *e;       // [S][n][n] FP32 correction added to p (OUT_PUPD)
+    const double *K64;    // [S][n][n] stage coefficient in FP64
+    float *r32;           // [S][n][n] the residual, rounded to FP32
 };
 
 // Launches one fused smoothing pass; nhalf = number of half-sweeps (2 nu),

@@ -13,6 +13,9 @@
 // residual follows at row F - NH - 1 and is summed over 2x2 blocks into the
 // next coarser grid and/or squared into the sample's residual norm. Every
 // cell is read and written once per pass.
+// The pre-smoothing pass of an FP32 cycle that follows an FP64 refinement can
+// take the refinement itself (INIT_IR): the residual of each row, formed in
+// FP64 one row ahead of the sweeps, is that row's right-hand side.
 // Rows in flight live in an LDS ring padded with a zero column on each side,
 // and the ring rows below row 0 and above row n-1 read as zero when those rows
 // are swept, so boundary neighbours contribute nothing without a branch (a
@@ -106,6 +109,14 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
     constexpr bool LX = (INIT == INIT_LOAD || INIT == INIT_PROLONG);
+    // INIT_IR: the FP64 refinement of the stage iterate runs one row ahead of the
+    // sweeps. At step F row F + 1 of p (+ e) and K64 enters their LDS rings; after
+    // the step's barrier the residual of row F is formed in FP64 and, rounded to
+    // FP32, is row F's right-hand side (and K of row F is float(K64))
+    constexpr bool IR = (INIT == INIT_IR);
+    constexpr bool PU = IR && (OUT & OUT_PUPD) != 0;
+    static_assert(!IR || (sizeof(T) == 4 && CK && RHSA && (OUT & ~OUT_PUPD) == OUT_RESTRICT),
+                  "the refinement start is an FP32 pre-smoothing pass of the stage operator");
     const int n = A.n, nl = n >> 1, nc = n >> 1;
     const int l = threadIdx.x;
     const int s = blockIdx.x;
@@ -117,6 +128,10 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     T *ks = xs + RX * XS;                               // [4][n] K (stage) or west faces (correction)
     T *cs = ks + 4 * n;                                 // [4][nc] coarse rows (prolongation source)
     T *red = cs + 4 * nc;                               // [16]
+    // INIT_IR (in place of ks, cs and red, which it does not use)
+    double *ks64 = reinterpret_cast<double *>(xs + RX * XS);  // [4][n] K64 rows
+    double *ps64 = ks64 + 4 * n;                             // [3][n] rows of p (+ e)
+    double *red64 = ps64 + 3 * n;                            // [18]
     for (int k = l; k < RX * XS; k += blockDim.x) xs[k] = T(0);
     __syncthreads();
 
@@ -147,9 +162,46 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
             qc[slot] = A.xc[cbase + size_t(J) * nc + l];
         }
     };
+    // INIT_IR: the next row of p, e and K64 in flight (one row: the unroll's five
+    // rows in flight took 209 VGPRs, two waves per SIMD, and measured 2.6% slower
+    // than this at three), held as vector types (the compiler kept the pair
+    // struct in scratch memory here)
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    d2v qp{0.0, 0.0}, qk64{0.0, 0.0};
+    f2v qe2{0.0f, 0.0f};
+    auto fetch_ir = [&](int row) __attribute__((always_inline)) {
+        if constexpr (IR) {
+            const size_t idx = base + size_t(row) * n + 2 * l;
+            qp = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(A.p + idx));
+            if constexpr (PU) qe2 = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(A.e + idx));
+            qk64 = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(A.K64 + idx));
+        }
+    };
+    if constexpr (IR) {
+        fetch_ir(0);
+    } else {
 #pragma unroll
-    for (int u = 0; u < D; ++u)
-        if (u < n) fetch(u, u);
+        for (int u = 0; u < D; ++u)
+            if (u < n) fetch(u, u);
+    }
+    // INIT_IR state: this lane's pairs of p (+ e) of the rows below / at / above
+    // the residual's row, K64 of the residual's row and the one above, the north
+    // faces of the row below (south faces of the residual's row), ||r||^2 and Q
+    V2<double> pdn{0.0, 0.0}, pmid{0.0, 0.0}, pup{0.0, 0.0}, kmid{0.0, 0.0}, kup{0.0, 0.0}, tnp{0.0, 0.0};
+    double rr64 = 0.0, q64 = 0.0;
+    if constexpr (IR) {  // row 0 enters
+        V2<double> pv{qp.x, qp.y};
+        if constexpr (PU) {
+            pv.a += double(qe2.x);
+            pv.b += double(qe2.y);
+        }
+        pmid = pv;
+        kmid = V2<double>{qk64.x, qk64.y};
+        st2(ps64 + 2 * l, pv.a, pv.b);
+        st2(ks64 + 2 * l, kmid.a, kmid.b);
+        fetch_ir(1);
+    }
 
     // coefficient ring, slot = row % U: faces west of cell 0, between the cells,
     // east of cell 1; south / north faces and 1/diagonal of both cells; rhs
@@ -175,12 +227,14 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // VGPRs, and 58 KB of LDS at 512^2). The other passes read them from the LDS
     // ring: their register rings leave no room (the FP32 eight-half-sweep pass
     // drops from 252 VGPRs, two waves per SIMD, to 162, three; the FP64
-    // correction passes would spill).
-    constexpr bool RC = (sizeof(T) == 4 && NH < 6) || (sizeof(T) == 8 && CK && !RHSA);
-    // FP64 and the long FP32 passes: 1/diagonal recomputed in each half-sweep
-    // from the coefficient ring instead of being held in a ring of its own; the
-    // registers this frees keep the FP64 correction passes from spilling
-    constexpr bool RI = sizeof(T) == 8 || NH >= 6;
+    // correction passes would spill; the refinement start, whose FP64 state
+    // takes the room, keeps three waves per SIMD so, at 156-163 VGPRs).
+    constexpr bool RC = (sizeof(T) == 4 && NH < 6 && !IR) || (sizeof(T) == 8 && CK && !RHSA);
+    // FP64, the long FP32 passes and the refinement start: 1/diagonal recomputed
+    // in each half-sweep from the coefficient ring instead of being held in a
+    // ring of its own; the registers this frees keep the FP64 correction passes
+    // from spilling
+    constexpr bool RI = sizeof(T) == 8 || NH >= 6 || IR;
     V2<T> hv[NH + 1];
 #pragma unroll
     for (int t = 0; t <= NH; ++t) hv[t] = V2<T>{T(0), T(0)};
@@ -195,12 +249,13 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // of its queues in scratch memory); straight-line steps only in the
     // pre-smoothing passes of the stage operator, checked steps elsewhere.
     if constexpr (sizeof(T) == 4) {
-        auto step = [&](const int F, const int u, auto chk) {
+        auto step = [&](const int F, const int u, auto chk) __attribute__((always_inline)) {
             constexpr bool C = decltype(chk)::value;
 #include "march_step.inc"
         };
         const int lo = ((NH + 1 + U - 1) / U) * U;       // first unchecked step
-        const int hi = max(lo, ((n - U) / U) * U);         // first checked step after them
+        // first checked step after them
+        const int hi = max(lo, ((n - U) / U) * U);
         int F0 = 0;
         for (; F0 < lo; F0 += U) {
 #pragma unroll
@@ -259,6 +314,18 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
             }
         }
     }
+    if constexpr (IR) {
+        const double t = block_sum(rr64, red64);
+        if (threadIdx.x == 0) A.rr[s] = t;
+        if (!dns) {
+            if (last) A.q[s] = q64;
+        } else {
+            if (l == (n >> 2) - 1) red64[16] = q64;
+            if (l == (n >> 2)) red64[17] = q64;
+            __syncthreads();
+            if (l == 0) A.q[s] = (red64[16] + red64[17]) * 0.25;
+        }
+    }
     if (OUT & OUT_RR) {
         const T t = block_sum(rr, red);
         if (threadIdx.x == 0) A.rr[s] = double(t);
@@ -282,7 +349,9 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
                           hipStream_t st) {
     const int n = a.n;
     const size_t lds =
-        (size_t(march_ring_rows(NH)) * (n + 4) + 4 * size_t(n) + 4 * size_t(n / 2) + 16) * sizeof(T);
+        init == INIT_IR
+            ? size_t(march_ring_rows(NH)) * (n + 4) * sizeof(T) + (7 * size_t(n) + 18) * sizeof(double)
+            : (size_t(march_ring_rows(NH)) * (n + 4) + 4 * size_t(n) + 4 * size_t(n / 2) + 16) * sizeof(T);
     dim3 grid(S), block(n / 2);
 #define FMGMC_MARCH_CASE(CKV, INITV, RHSV, OUTV)                                               \
     if (ck == CKV && init == INITV && rhsa == RHSV && out == (OUTV)) {                         \
@@ -301,6 +370,12 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
         // FP32 cycles back to back: prolongation and post-smoothing of one
         // cycle, then pre-smoothing and restriction of the next, in one pass
         FMGMC_MARCH_CASE(true, INIT_PROLONG, true, OUT_RESTRICT)
+        if constexpr (NH <= 4) {
+            // FP64 refinement of the stage iterate and the pre-smoothing and
+            // restriction of the next FP32 cycle, in one pass
+            FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT)
+            FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_PUPD)
+        }
     }
     // correction operators (levels below the top)
     FMGMC_MARCH_CASE(false, INIT_ZERO, true, OUT_RESTRICT)

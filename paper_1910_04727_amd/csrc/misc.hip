@@ -11,7 +11,9 @@ namespace fmgmc {
 
 namespace {
 
-__device__ __forceinline__ double harm_d(double a, double b) { return 2.0 * a * b / (a + b); }
+// transmissibility 2ab/(a+b) through the refined reciprocal, as in the
+// marching passes (so the fused refinement forms the same operator)
+__device__ __forceinline__ double harm_d(double a, double b) { return 2.0 * a * b * rcp_(a + b); }
 
 // Refinement pass, marching over rows (one workgroup per sample, one lane per
 // column): p <- p + e; r = b - A p in FP64 with the stage operator; r is

@@ -203,7 +203,7 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    PROF_KINDS = ("pre", "post", "ir", "kl", "small", "cnn", "fused")
+    PROF_KINDS = ("pre", "post", "ir", "kl", "small", "cnn", "fused", "irpre")
 
     def profile(self, enable=True):
         _check(lib().fmgmc_profile_enable(self._h, 1 if enable else 0))

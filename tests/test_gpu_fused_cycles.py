@@ -71,12 +71,19 @@ def test_fused_matches_separate_and_oracle(nu):
     qf1, qc1, cyc1, p1 = res[True]
     qf0, qc0, cyc0, p0 = res[False]
     fusable = nu[0] + nu[1] <= 4
+    fuse_ir = fusable and nu[0] <= 2
     # three joins among the four FP32 cycles before the first refinement, on the 256^2 top grid
     assert p1["fused"][1] == (3 if fusable else 0)
-    assert p0["fused"][1] == 0
+    assert p0["fused"][1] == 0 and p0["irpre"][1] == 0
     if fusable and np.array_equal(cyc1, cyc0):
         # each join replaces one post- and one pre-smoothing pass of the top grid
-        assert p1["pre"][1] == p0["pre"][1] - 3 and p1["post"][1] == p0["post"][1] - 3
+        assert p1["post"][1] == p0["post"][1] - 3
+        if fuse_ir:
+            # every refinement pass also does the next cycle's pre-smoothing, so no
+            # cycle on the top grid has a pre-smoothing pass of its own
+            assert p1["pre"][1] == 0 and p1["ir"][1] == 0 and p1["irpre"][1] == p0["ir"][1]
+        else:
+            assert p1["pre"][1] == p0["pre"][1] - 3 and p1["irpre"][1] == 0
     d = max(np.max(np.abs(qf1 - qf0) / np.abs(qf0)), np.max(np.abs(qc1 - qc0) / np.abs(qc0)))
     oqf, oqc, _, _ = oracle(cfg, n, level, xi, tol=1e-12, max_cycles=80, wmax=32)
     e1 = max(np.max(np.abs(qf1 - oqf) / np.abs(oqf)), np.max(np.abs(qc1 - oqc) / np.abs(oqc)))
