@@ -101,7 +101,7 @@ def run_form(torch, fmgmc, xi_dev, form, args, tol=None, steps=None, warmup=None
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes calibrated on a plain 1 GiB copy
 # (profiles/hbm_traffic_512.md; taken offline, not in this run). None once a
 # kernel changes after measurement.
-TRAFFIC_RATIO = {"ir": 1.000, "post": 1.000, "pre": 1.000, "fused": 1.000, "irpre": None}
+TRAFFIC_RATIO = {"ir": None, "post": 1.000, "pre": 1.000, "fused": 1.000, "irpre": 1.000}
 TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE / WRITE_SIZE passes over the same launch, calibrated on a plain "
                   "copy (profiles/hbm_traffic_512.md); taken offline, not in this run")
 STENCIL_TARGET = 0.60  # fraction of the HBM peak the stencil passes aim for
