@@ -101,10 +101,16 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     constexpr int RX = march_ring_rows(NH);  // LDS x ring rows (>= NH + 3), power of two
     // prefetch distance of the load queue (a divisor of U, so that a row's queue
     // slot is a constant after unrolling, and row F + D lands in the slot that
-    // step F + D reads): U rows, or three in the FP32 passes of eight
+    // step F + D reads): U rows; three in the FP32 stage-grid passes of eight
     // half-sweeps, whose registers then fit three waves per SIMD (see RC
-    // below); the eight-half-sweep pass measured 7% faster so.
-    constexpr int D = (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3 : U;
+    // below; 7% faster so); one in the correction passes (coefficients from
+    // faces, grids below the stage grid), whose row steps are long enough to
+    // cover a load. The registers that frees (FP32 with RI below: 145-152 ->
+    // 99-109 VGPRs; FP64: 244-256 with a spill -> 186-194 without) take the FP32
+    // passes to four waves per SIMD, so that all 4096 one-wave workgroups of a
+    // 128^2 or 64^2 pass are resident at once (FP32+IR +1.3-2.7%, FP64 form
+    // +1.8%, same-box A/B).
+    constexpr int D = !CK ? 1 : (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3 : U;
     static_assert(U % D == 0, "the load queue depth must divide the unroll");
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
@@ -230,11 +236,10 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // correction passes would spill; the refinement start, whose FP64 state
     // takes the room, keeps three waves per SIMD so, at 156-163 VGPRs).
     constexpr bool RC = (sizeof(T) == 4 && NH < 6 && !IR) || (sizeof(T) == 8 && CK && !RHSA);
-    // FP64, the long FP32 passes and the refinement start: 1/diagonal recomputed
-    // in each half-sweep from the coefficient ring instead of being held in a
-    // ring of its own; the registers this frees keep the FP64 correction passes
-    // from spilling
-    constexpr bool RI = sizeof(T) == 8 || NH >= 6 || IR;
+    // FP64, the long FP32 passes, the refinement start and the correction
+    // passes: 1/diagonal recomputed in each half-sweep from the coefficient ring
+    // instead of being held in a ring of its own (registers, see D above)
+    constexpr bool RI = sizeof(T) == 8 || NH >= 6 || IR || !CK;
     V2<T> hv[NH + 1];
 #pragma unroll
     for (int t = 0; t <= NH; ++t) hv[t] = V2<T>{T(0), T(0)};
