@@ -224,18 +224,20 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     V2<T> bprev{T(0), T(0)}, bcur{T(0), T(0)};
     T eprev = T(0), ecur = T(0);                 // east boundary face of rows F-1, F (correction)
     T rprev = T(0), rr = T(0), q = T(0);
-    // FP32 passes of up to four half-sweeps, and the FP64 stage-operator passes
-    // with boundary-data right-hand sides: this lane's cell pairs of the rows in
-    // flight (hv[t], the row that half-sweep t acted on last; hv[0], the row that
-    // entered last; hres, the row below the residual's row), so that the sweeps
-    // read only the west / east neighbours from LDS. In FP64 that halves the LDS
-    // traffic that bounds these passes (two waves per SIMD either way: 206
-    // VGPRs, and 58 KB of LDS at 512^2). The other passes read them from the LDS
-    // ring: their register rings leave no room (the FP32 eight-half-sweep pass
-    // drops from 252 VGPRs, two waves per SIMD, to 162, three; the FP64
-    // correction passes would spill; the refinement start, whose FP64 state
+    // FP32 passes of up to four half-sweeps, the FP64 stage-operator passes
+    // with boundary-data right-hand sides and the FP64 correction passes: this
+    // lane's cell pairs of the rows in flight (hv[t], the row that half-sweep t
+    // acted on last; hv[0], the row that entered last; hres, the row below the
+    // residual's row), so that the sweeps read only the west / east neighbours
+    // from LDS. In FP64 that halves the LDS traffic that bounds these passes (two
+    // waves per SIMD either way: 206 VGPRs and 58 KB of LDS at 512^2 for the
+    // stage operator; 218-238 VGPRs for the correction passes, which fit it
+    // without a spill since their load queue holds one row: +0.7%, bitwise
+    // unchanged). The other passes read them from the LDS ring: their register
+    // rings leave no room (the FP32 eight-half-sweep pass drops from 252 VGPRs,
+    // two waves per SIMD, to 162, three; the refinement start, whose FP64 state
     // takes the room, keeps three waves per SIMD so, at 156-163 VGPRs).
-    constexpr bool RC = (sizeof(T) == 4 && NH < 6 && !IR) || (sizeof(T) == 8 && CK && !RHSA);
+    constexpr bool RC = (sizeof(T) == 4 && NH < 6 && !IR) || (sizeof(T) == 8 && (!CK || !RHSA));
     // FP64, the long FP32 passes, the refinement start and the correction
     // passes: 1/diagonal recomputed in each half-sweep from the coefficient ring
     // instead of being held in a ring of its own (registers, see D above)
