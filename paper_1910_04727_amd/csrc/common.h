@@ -31,6 +31,16 @@ __device__ __forceinline__ double rcp_(double x) {
     return fma(y, e, y);
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup i to XCD
+// i mod 8), each XCD with its own L2. xcd_unit maps workgroup L of T to a work
+// unit so that every XCD takes one contiguous range of units: neighbouring
+// units (consecutive rows of one sample) that read the same input rows then
+// meet in the same L2 instead of fetching them from HBM once per XCD.
+__device__ __forceinline__ int xcd_unit(int L, int T) {
+    const int q = T >> 3, r = T & 7, x = L & 7;
+    return x * q + min(x, r) + (L >> 3);
+}
+
 // ---------------------------------------------------------------- KL table
 struct ModeTable {
     int M = 0;

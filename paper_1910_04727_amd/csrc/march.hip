@@ -423,8 +423,11 @@ template <typename T>
 __global__ void k_faces_from_k(int n, const T *__restrict__ K, Faces<T> out, int nc, int all) {
     // coarse cell (I, J) of the n/2 grid from the four faces of the fine operator on it:
     // K of fine rows 2J-1, 2J, 2J+1 at columns 2I-1, 2I, 2I+1 (cell pairs as one load)
-    const int s = blockIdx.y;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    // workgroup -> (sample, chunk of coarse rows), XCD-contiguous: fine row
+    // 2J - 1 is also read by the workgroup of coarse row J - 1
+    const int u = xcd_unit(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int s = u / gridDim.x;
+    const int c = (u - s * gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= nc * nc) return;
     const int I = c & (nc - 1), J = c >> (31 - __builtin_clz(nc));
     const int i0 = 2 * I, j0 = 2 * J;
@@ -446,8 +449,9 @@ __global__ void k_faces_from_k(int n, const T *__restrict__ K, Faces<T> out, int
 
 template <typename T>
 __global__ void k_faces_coarsen(int n, Faces<T> in, Faces<T> out, int nc) {
-    const int s = blockIdx.y;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = xcd_unit(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int s = u / gridDim.x;
+    const int c = (u - s * gridDim.x) * blockDim.x + threadIdx.x;
     if (c >= nc * nc) return;
     const int I = c % nc, J = c / nc;
     const size_t fb = size_t(s) * n * n;

@@ -128,10 +128,13 @@ __global__ __launch_bounds__(1024) void k_ir(IRArgs A) {
 // 16-byte row pairs.
 template <typename TS>
 __global__ void k_interp64(int n, const TS *xc, double *p, const int32_t *active, Bnd g) {
-    const int s = blockIdx.y;
+    // workgroup -> (sample, chunk of coarse rows), XCD-contiguous: the three
+    // workgroups that read a coarse row share an L2
+    const int u = xcd_unit(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int s = u / gridDim.x, bx = u - s * gridDim.x;
     if (active && active[s] == 0) return;
     const int nc = n / 2;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = bx * blockDim.x + threadIdx.x;
     if (c >= nc * nc) return;
     const int lgc = 31 - __builtin_clz(nc);
     const int I = c & (nc - 1), J = c >> lgc;
