@@ -490,22 +490,35 @@ int run_block(Work &W, bool use_graph, std::tuple<int, int, int, int> key, hipSt
     return FMGMC_OK;
 }
 
-// Build correction pyramids and coarsest inverses for a batch.
+// Correction pyramid q of the QoI stage `top`: its faces on n_top/2 from K
+// (unless a pass over the stage grid has written them), coarsened level by
+// level, and the inverse of its coarsest operator.
 template <typename T>
-int prepare(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int level, int t, hipStream_t st) {
+int pyramid(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int q, int top, bool from_k, hipStream_t st) {
     const int all = bnd(c).all;
     const int N0 = W.nsz[0] * W.nsz[0];
+    if (from_k) TRY(launch_faces_from_k<T>(W.nsz[top], B.K[top], all, B.pf[q].f[top - 1], S, st));
+    for (int j = top - 1; j >= 1; --j)
+        TRY(launch_faces_coarsen<T>(W.nsz[j], B.pf[q].f[j], B.pf[q].f[j - 1], S, st));
+    return launch_chol<T>(W.nsz[0], nullptr, B.pf[q].f[0], false, all, W.chol + size_t(1 + q) * S * N0 * N0, S,
+                          st);
+}
+
+// Build correction pyramids and coarsest inverses for a batch. With skip_top,
+// the pyramid of the level's top stage (q = 1, used by that stage only when
+// level >= 1) is left to the stage itself: its first refinement pass writes the
+// faces on n_top/2 (fmgmc::pyramid then runs from there).
+template <typename T>
+int prepare(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int level, int t, hipStream_t st, bool skip_top = false) {
+    const int all = bnd(c).all;
     Faces<T> none{};
     TRY(launch_chol<T>(W.nsz[0], B.K[0], none, true, all, W.chol, S, st));
     for (int q = 0; q < 2; ++q) {
         const int top = (q == 1) ? t : t - 1;  // QoI stage that owns the pyramid
         if (q == 0 && level == 0) continue;
         if (top < 1) continue;
-        TRY(launch_faces_from_k<T>(W.nsz[top], B.K[top], all, B.pf[q].f[top - 1], S, st));
-        for (int j = top - 1; j >= 1; --j)
-            TRY(launch_faces_coarsen<T>(W.nsz[j], B.pf[q].f[j], B.pf[q].f[j - 1], S, st));
-        TRY(launch_chol<T>(W.nsz[0], nullptr, B.pf[q].f[0], false, all, W.chol + size_t(1 + q) * S * N0 * N0, S,
-                           st));
+        if (q == 1 && skip_top) continue;
+        TRY(pyramid<T>(c, W, B, S, q, top, true, st));
     }
     return FMGMC_OK;
 }
@@ -652,7 +665,13 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
                  hipStream_t st) {
     const int t = ilog2((c->hier.n0 << level) / W.nsz[0]);
     Bufs<float> B = bufs32(W);
-    TRY(prepare<float>(c, W, B, S, level, t, st));
+    // refinement passes fused with the next cycle's pre-smoothing (see the stage
+    // loop); then the top stage's first one also writes the faces of its
+    // correction pyramid (pyramid 1 serves only the top stage when level >= 1)
+    const bool fuse_ir_top = c->opts.fuse_cycles && t > c->small_top && c->opts.nu1 <= 2 &&
+                             c->opts.nu1 + c->opts.nu2 <= 4;
+    const bool top_faces = fuse_ir_top && level >= 1;
+    TRY(prepare<float>(c, W, B, S, level, t, st, top_faces));
     const double tol = c->opts.rel_tol;
     const Bnd g = bnd(c);
     // one FMG pass up to stage ktop; with_coarse: stage ktop - 1 is a QoI stage too
@@ -694,7 +713,7 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             // float(K64), the stage's FP32 K
             const bool fuse_ir = fuse && c->opts.nu1 <= 2;
             // refinement pass: p (+= e), r = b - A p in FP64, r -> FP32, ||r||^2, Q
-            auto refine = [&](const IRArgs &a) -> int {
+            auto refine = [&](const IRArgs &a, bool faces = false) -> int {
                 const double cells = double(W.n_active_host) * double(n) * n;
                 if (!fuse_ir) {
                     // reads p, e and K, writes p and r (without e: reads p and K, writes r)
@@ -714,9 +733,12 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
                 m.e = a.e;
                 m.K64 = a.K;
                 m.r32 = a.r32;
-                const int out = OUT_RESTRICT | (a.e ? OUT_PUPD : 0);
-                // the refinement's bytes, then x and the restricted residual out
-                const double b = cells * ((a.e ? 8.0 + 4.0 + 8.0 + 8.0 + 4.0 : 8.0 + 8.0 + 4.0) + 4.0 + 1.0);
+                if (faces) m.f = B.pf[1].f[k - 1];
+                const int out = OUT_RESTRICT | (a.e ? OUT_PUPD : 0) | (faces ? OUT_FACES : 0);
+                // the refinement's bytes, then x and the restricted residual out (and
+                // the west and south faces on n/2)
+                const double b = cells * ((a.e ? 8.0 + 4.0 + 8.0 + 8.0 + 4.0 : 8.0 + 8.0 + 4.0) + 4.0 + 1.0 +
+                                          (faces ? 2.0 : 0.0));
                 auto go = [&] { return launch_march(m, S, 2 * c->opts.nu1, true, INIT_IR, true, out, st); };
                 if (k == W.top_grid) return timed(c, W, FMGMC_PROF_IRPRE, b, st, go);
                 return go();
@@ -724,12 +746,16 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             const bool warm = c->warm && n >= c->warm_min_n && (c->warm_max_n == 0 || n <= c->warm_max_n);
             // first residual of the stage (with the warm start, the network's input:
             // a plain refinement pass, the warm start's own passes then do the rest)
+            // the faces of the top stage's pyramid (skipped by prepare): from this pass
+            const bool faces_here = top_faces && k == t;
             if (warm && fuse_ir) {
                 const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
                 if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
                 else TRY(launch_ir(ia, S, st));
+                if (faces_here) TRY(pyramid<float>(c, W, B, S, 1, t, true, st));
             } else {
-                TRY(refine(ia));
+                TRY(refine(ia, faces_here));
+                if (faces_here) TRY(pyramid<float>(c, W, B, S, 1, t, false, st));
             }
             float *capx = W.cap_x[slot], *capt = W.cap_t[slot];
             if (warm || capx) TRY(launch_copy_f64(W.rr, W.rr0, S, st));

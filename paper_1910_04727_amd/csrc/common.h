@@ -77,8 +77,11 @@ struct Faces {
 // INIT_IR (FP32, stage operator): zero start; the right-hand side of each row
 // is the FP64 refinement residual of the stage iterate p, formed in the same
 // pass (with OUT_PUPD, p += e first and p written back), and K = float(K64).
+// OUT_FACES (INIT_IR without OUT_PUPD): the pass also writes the correction
+// faces on n/2 (f), those that k_faces_from_k forms from K, from its own
+// coefficient ring.
 enum { INIT_ZERO = 0, INIT_LOAD = 1, INIT_PROLONG = 2, INIT_INTERP = 3, INIT_IR = 4 };
-enum { OUT_RESTRICT = 1, OUT_RR = 2, OUT_Q = 4, OUT_PUPD = 8 };
+enum { OUT_RESTRICT = 1, OUT_RR = 2, OUT_Q = 4, OUT_PUPD = 8, OUT_FACES = 16 };
 
 template <typename T>
 struct MarchArgs {

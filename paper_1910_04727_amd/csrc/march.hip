@@ -121,8 +121,11 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // FP32, is row F's right-hand side (and K of row F is float(K64))
     constexpr bool IR = (INIT == INIT_IR);
     constexpr bool PU = IR && (OUT & OUT_PUPD) != 0;
-    static_assert(!IR || (sizeof(T) == 4 && CK && RHSA && (OUT & ~OUT_PUPD) == OUT_RESTRICT),
+    static_assert(!IR || (sizeof(T) == 4 && CK && RHSA && (OUT & ~(OUT_PUPD | OUT_FACES)) == OUT_RESTRICT),
                   "the refinement start is an FP32 pre-smoothing pass of the stage operator");
+    // OUT_FACES: coarse faces written as the coefficients of each odd row are formed
+    constexpr bool FO = (OUT & OUT_FACES) != 0;
+    static_assert(!FO || (IR && !(OUT & OUT_PUPD)), "faces are written by the stage's first refinement");
     const int n = A.n, nl = n >> 1, nc = n >> 1;
     const int l = threadIdx.x;
     const int s = blockIdx.x;
@@ -382,6 +385,7 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
             // restriction of the next FP32 cycle, in one pass
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT)
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_PUPD)
+            FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_FACES)
         }
     }
     // correction operators (levels below the top)
