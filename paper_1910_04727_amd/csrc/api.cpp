@@ -693,7 +693,20 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
                 if (fine && with_coarse) return launch_interp64<double>(n, W.p64[k - 1], W.p64[k], W.active, g, S, st);
                 return launch_interp64<float>(n, W.x32[k - 1], W.p64[k], W.active, g, S, st);
             };
-            TRY(interp());
+            // back-to-back cycles on a marching top grid share their joining pass
+            const bool fuse = c->opts.fuse_cycles && k > c->small_top && c->opts.nu1 + c->opts.nu2 <= 4;
+            // ... and every refinement also does the pre-smoothing and restriction of
+            // the FP32 cycle after it (which then skips its own): the refinement's
+            // residual is that cycle's right-hand side, and its coefficients are
+            // float(K64), the stage's FP32 K
+            const bool fuse_ir = fuse && c->opts.nu1 <= 2;
+            const bool warm = c->warm && n >= c->warm_min_n && (c->warm_max_n == 0 || n <= c->warm_max_n);
+            // the faces of the top stage's pyramid (skipped by prepare) come from its
+            // first refinement pass, which also forms the FMG start from the FP64
+            // solution below it (the separate interpolation pass is then not run)
+            const bool faces_here = top_faces && k == t;
+            const bool pin = faces_here && fuse_ir && !warm && fine && with_coarse;
+            if (!pin) TRY(interp());
             TRY(launch_bnorm<double>(n, W.K64[k], g, W.bnorm, S, st));
             IRArgs ia{};
             ia.n = n;
@@ -705,15 +718,8 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
             ia.q = W.q;
             ia.active = W.active;
             ia.g = g;
-            // back-to-back cycles on a marching top grid share their joining pass
-            const bool fuse = c->opts.fuse_cycles && k > c->small_top && c->opts.nu1 + c->opts.nu2 <= 4;
-            // ... and every refinement also does the pre-smoothing and restriction of
-            // the FP32 cycle after it (which then skips its own): the refinement's
-            // residual is that cycle's right-hand side, and its coefficients are
-            // float(K64), the stage's FP32 K
-            const bool fuse_ir = fuse && c->opts.nu1 <= 2;
             // refinement pass: p (+= e), r = b - A p in FP64, r -> FP32, ||r||^2, Q
-            auto refine = [&](const IRArgs &a, bool faces = false) -> int {
+            auto refine = [&](const IRArgs &a, bool faces = false, bool pstart = false) -> int {
                 const double cells = double(W.n_active_host) * double(n) * n;
                 if (!fuse_ir) {
                     // reads p, e and K, writes p and r (without e: reads p and K, writes r)
@@ -734,27 +740,27 @@ int run_batch_ir(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, double
                 m.K64 = a.K;
                 m.r32 = a.r32;
                 if (faces) m.f = B.pf[1].f[k - 1];
-                const int out = OUT_RESTRICT | (a.e ? OUT_PUPD : 0) | (faces ? OUT_FACES : 0);
+                if (pstart) m.pc = W.p64[k - 1];
+                const int out = OUT_RESTRICT | (a.e ? OUT_PUPD : 0) | (faces ? OUT_FACES : 0) |
+                                (pstart ? OUT_PINTERP : 0);
                 // the refinement's bytes, then x and the restricted residual out (and
-                // the west and south faces on n/2)
+                // the west and south faces on n/2; with the start formed in the pass, p
+                // is written instead of read and the solution on n/2 read)
                 const double b = cells * ((a.e ? 8.0 + 4.0 + 8.0 + 8.0 + 4.0 : 8.0 + 8.0 + 4.0) + 4.0 + 1.0 +
-                                          (faces ? 2.0 : 0.0));
+                                          (faces ? 2.0 : 0.0) + (pstart ? 2.0 : 0.0));
                 auto go = [&] { return launch_march(m, S, 2 * c->opts.nu1, true, INIT_IR, true, out, st); };
                 if (k == W.top_grid) return timed(c, W, FMGMC_PROF_IRPRE, b, st, go);
                 return go();
             };
-            const bool warm = c->warm && n >= c->warm_min_n && (c->warm_max_n == 0 || n <= c->warm_max_n);
             // first residual of the stage (with the warm start, the network's input:
             // a plain refinement pass, the warm start's own passes then do the rest)
-            // the faces of the top stage's pyramid (skipped by prepare): from this pass
-            const bool faces_here = top_faces && k == t;
             if (warm && fuse_ir) {
                 const double irb0 = double(W.n_active_host) * double(n) * n * (8.0 + 8.0 + 4.0);
                 if (k == W.top_grid) TRY(timed(c, W, FMGMC_PROF_IR, irb0, st, [&] { return launch_ir(ia, S, st); }));
                 else TRY(launch_ir(ia, S, st));
                 if (faces_here) TRY(pyramid<float>(c, W, B, S, 1, t, true, st));
             } else {
-                TRY(refine(ia, faces_here));
+                TRY(refine(ia, faces_here, pin));
                 if (faces_here) TRY(pyramid<float>(c, W, B, S, 1, t, false, st));
             }
             float *capx = W.cap_x[slot], *capt = W.cap_t[slot];

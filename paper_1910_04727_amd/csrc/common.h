@@ -79,9 +79,11 @@ struct Faces {
 // pass (with OUT_PUPD, p += e first and p written back), and K = float(K64).
 // OUT_FACES (INIT_IR without OUT_PUPD): the pass also writes the correction
 // faces on n/2 (f), those that k_faces_from_k forms from K, from its own
-// coefficient ring.
+// coefficient ring. OUT_PINTERP (with OUT_FACES): p is not read but formed as
+// the FMG interpolation of the FP64 solution on n/2 (pc), as k_interp64 forms
+// it, and written.
 enum { INIT_ZERO = 0, INIT_LOAD = 1, INIT_PROLONG = 2, INIT_INTERP = 3, INIT_IR = 4 };
-enum { OUT_RESTRICT = 1, OUT_RR = 2, OUT_Q = 4, OUT_PUPD = 8, OUT_FACES = 16 };
+enum { OUT_RESTRICT = 1, OUT_RR = 2, OUT_Q = 4, OUT_PUPD = 8, OUT_FACES = 16, OUT_PINTERP = 32 };
 
 template <typename T>
 struct MarchArgs {
@@ -99,6 +101,7 @@ struct MarchArgs {
     // INIT_IR only: the refinement's operands (rr and q then take its FP64
     // residual norm and QoI)
     double *p;            // [S][n][n] FP64 stage iterate
+    const double *pc;     // [S][n/2][n/2] FP64 solution on n/2 (OUT_PINTERP)
     const float *e;       // [S][n][n] FP32 correction added to p (OUT_PUPD)
     const double *K64;    // [S][n][n] stage coefficient in FP64
     float *r32;           // [S][n][n] the residual, rounded to FP32

@@ -95,8 +95,16 @@ __device__ __forceinline__ T block_sum(T v, T *red) {
 // their lower neighbour and the row whose residual is formed
 constexpr int march_ring_rows(int nh) { return nh + 3 <= 8 ? 8 : 16; }
 
+// minimum waves per SIMD the register allocation must allow: three for the
+// refinement start with the interpolated iterate (167 VGPRs and 36 B per lane
+// spilled; left alone the compiler takes 173 VGPRs, two waves per SIMD, and
+// the pass measured 12% slower at 512^2)
+template <int INIT, int OUT>
+constexpr int march_min_waves() { return (INIT == INIT_IR && (OUT & OUT_PINTERP)) ? 3 : 1; }
+
 template <typename T, int NH, bool CK, int INIT, bool RHSA, int OUT>
-__global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(march_min_waves<INIT, OUT>())))
+void k_march(MarchArgs<T> A) {
     constexpr int U = NH + 1;    // register ring depth = unroll
     constexpr int RX = march_ring_rows(NH);  // LDS x ring rows (>= NH + 3), power of two
     // prefetch distance of the load queue (a divisor of U, so that a row's queue
@@ -121,11 +129,18 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // FP32, is row F's right-hand side (and K of row F is float(K64))
     constexpr bool IR = (INIT == INIT_IR);
     constexpr bool PU = IR && (OUT & OUT_PUPD) != 0;
-    static_assert(!IR || (sizeof(T) == 4 && CK && RHSA && (OUT & ~(OUT_PUPD | OUT_FACES)) == OUT_RESTRICT),
+    static_assert(!IR || (sizeof(T) == 4 && CK && RHSA && (OUT & ~(OUT_PUPD | OUT_FACES | OUT_PINTERP)) == OUT_RESTRICT),
                   "the refinement start is an FP32 pre-smoothing pass of the stage operator");
     // OUT_FACES: coarse faces written as the coefficients of each odd row are formed
     constexpr bool FO = (OUT & OUT_FACES) != 0;
     static_assert(!FO || (IR && !(OUT & OUT_PUPD)), "faces are written by the stage's first refinement");
+    // OUT_PINTERP: row F + 1 of p formed at step F from a 4-row LDS ring of coarse
+    // rows (slot = row & 3; the ghost rows -1 and n/2 in slots 3 and (n/2) & 3):
+    // coarse row (F + 3) / 2 enters at odd steps F (rows 0 and 1 before the
+    // first), so that the rows a step reads were written before its barrier and
+    // the row it writes is none of them
+    constexpr bool PI = (OUT & OUT_PINTERP) != 0;
+    static_assert(!PI || FO, "the interpolated start is the top stage's first refinement");
     const int n = A.n, nl = n >> 1, nc = n >> 1;
     const int l = threadIdx.x;
     const int s = blockIdx.x;
@@ -141,10 +156,26 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     double *ks64 = reinterpret_cast<double *>(xs + RX * XS);  // [4][n] K64 rows
     double *ps64 = ks64 + 4 * n;                             // [3][n] rows of p (+ e)
     double *red64 = ps64 + 3 * n;                            // [18]
+    double *cs64 = red64 + 18;                               // [4][n/2] coarse rows (PI)
+    const size_t base = size_t(s) * n * n;
+    // coarse row J of the solution on n/2 as it enters the ring: the ghost row
+    // n/2 is the mirror of row n/2 - 1 (no flow) or 2 g - it (Dirichlet, Case I)
+    const double *pcs = PI ? A.pc + size_t(s) * nc * nc : nullptr;
+    auto cload = [&](int J) -> double { return pcs[size_t(min(J, nc - 1)) * nc + l]; };
+    auto cput = [&](int J, double v) {
+        cs64[(J & 3) * nc + l] = (J == nc && A.g.all) ? 2.0 * A.g.n - v : v;
+    };
+    double qcd = 0.0;  // PI: the coarse value of the next row to enter
+    if constexpr (PI) {
+        const double v0 = cload(0), v1 = cload(1);
+        cput(0, v0);
+        cput(1, v1);
+        cs64[3 * nc + l] = A.g.all ? 2.0 * A.g.s - v0 : v0;  // ghost row -1
+        qcd = cload(2);
+    }
     for (int k = l; k < RX * XS; k += blockDim.x) xs[k] = T(0);
     __syncthreads();
 
-    const size_t base = size_t(s) * n * n;
     const size_t cbase = size_t(s) * nc * nc;
     const T gW = T(A.g.w), gE = T(A.g.e), gS = T(A.g.s), gN = T(A.g.n);
     const bool dns = A.g.all != 0;  // Dirichlet south / north sides (Case I)
@@ -182,7 +213,7 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     auto fetch_ir = [&](int row) __attribute__((always_inline)) {
         if constexpr (IR) {
             const size_t idx = base + size_t(row) * n + 2 * l;
-            qp = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(A.p + idx));
+            if constexpr (!PI) qp = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(A.p + idx));
             if constexpr (PU) qe2 = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(A.e + idx));
             qk64 = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(A.K64 + idx));
         }
@@ -199,8 +230,25 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs<T> A) {
     // faces of the row below (south faces of the residual's row), ||r||^2 and Q
     V2<double> pdn{0.0, 0.0}, pmid{0.0, 0.0}, pup{0.0, 0.0}, kmid{0.0, 0.0}, kup{0.0, 0.0}, tnp{0.0, 0.0};
     double rr64 = 0.0, q64 = 0.0;
+    // PI: fine row R of p, the FMG interpolation of the ring's coarse rows R/2 and
+    // the neighbour on R's side (ghosts at the boundary, as k_interp64 forms
+    // them), written as the stage's start
+    auto pinterp = [&](int R) -> V2<double> {
+        const int J0 = R >> 1, J1 = J0 + ((R & 1) ? 1 : -1);
+        const double *c0 = cs64 + (J0 & 3) * nc, *c1 = cs64 + (J1 & 3) * nc;
+        const double a0 = c0[l], a1 = c1[l];
+        const double w0 = first ? 2.0 * A.g.w - a0 : c0[max(l - 1, 0)];
+        const double w1 = first ? 2.0 * A.g.w - a1 : c1[max(l - 1, 0)];
+        const double e0 = last ? 2.0 * A.g.e - a0 : c0[min(l + 1, nc - 1)];
+        const double e1 = last ? 2.0 * A.g.e - a1 : c1[min(l + 1, nc - 1)];
+        const double p0 = (9.0 * a0 + 3.0 * w0 + 3.0 * a1 + w1) / 16.0;
+        const double p1 = (9.0 * a0 + 3.0 * e0 + 3.0 * a1 + e1) / 16.0;
+        st2_nt(A.p + base + size_t(R) * n + 2 * l, p0, p1);
+        return V2<double>{p0, p1};
+    };
     if constexpr (IR) {  // row 0 enters
         V2<double> pv{qp.x, qp.y};
+        if constexpr (PI) pv = pinterp(0);
         if constexpr (PU) {
             pv.a += double(qe2.x);
             pv.b += double(qe2.y);
@@ -360,7 +408,8 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
     const int n = a.n;
     const size_t lds =
         init == INIT_IR
-            ? size_t(march_ring_rows(NH)) * (n + 4) * sizeof(T) + (7 * size_t(n) + 18) * sizeof(double)
+            ? size_t(march_ring_rows(NH)) * (n + 4) * sizeof(T) +
+                  (7 * size_t(n) + 18 + ((out & OUT_PINTERP) ? 2 * size_t(n) : 0)) * sizeof(double)
             : (size_t(march_ring_rows(NH)) * (n + 4) + 4 * size_t(n) + 4 * size_t(n / 2) + 16) * sizeof(T);
     dim3 grid(S), block(n / 2);
 #define FMGMC_MARCH_CASE(CKV, INITV, RHSV, OUTV)                                               \
@@ -386,6 +435,7 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT)
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_PUPD)
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_FACES)
+            FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_FACES | OUT_PINTERP)
         }
     }
     // correction operators (levels below the top)
