@@ -237,22 +237,23 @@ __global__ __launch_bounds__(256) void k_kl_sep_f64(KLArgs A, int S) {
         }
         if (!pyr) continue;
         __syncthreads();
-        // the round's block: level-1 rows J1 = j0/2 + Jb, columns I1 = 32 rnd + Ib; level k
-        // takes the cells of level k - 1 with both indices even
+        // the round's block: level-1 rows J1 = j0/2 + Jb, columns I1 = 32 rnd + Ib. Its
+        // origin is a multiple of 32, so on level k (sh = k - 1 <= 5) it is the block of
+        // side 32 >> sh at the origin >> sh, whose cell (Jb, Ib) is level-1 cell
+        // (Jb, Ib) << sh; deeper, it holds the one cell at the origin >> sh if the
+        // origin is a multiple of 2^sh. Each level takes its own threads, a row of the
+        // block per group of lanes, so its stores are whole rows of the block
         const int J1b = j0 >> 1, I1b = (i0 - 16 * w) >> 1;
 #pragma unroll 1
-        for (int e = t; e < 32 * 32; e += 256) {
-            const int Jb = e >> 5, Ib = e & 31, J1 = J1b + Jb, I1 = I1b + Ib;
-            const double kv = L1[Jb * L1S + Ib];
-            int nl = n >> 1, jj = J1, ii = I1;
-            for (int k = 1; k < A.nlev; ++k) {
-                const size_t o = size_t(s) * nl * nl + size_t(jj) * nl + ii;
+        for (int k = 1, sh = 0; k < A.nlev; ++k, ++sh) {
+            const bool in = sh <= 5 || ((J1b | I1b) & ((1 << sh) - 1)) == 0;
+            const int side = in ? (sh <= 5 ? 32 >> sh : 1) : 0, lg = sh <= 5 ? 5 - sh : 0, nl = n >> k;
+            for (int e = t; e < side * side; e += 256) {
+                const int Jb = e >> lg, Ib = e & (side - 1);
+                const double kv = L1[(Jb << sh) * L1S + (Ib << sh)];
+                const size_t o = size_t(s) * nl * nl + size_t((J1b >> sh) + Jb) * nl + (I1b >> sh) + Ib;
                 if (A.K64[k]) A.K64[k][o] = kv;
                 if (A.K32[k]) A.K32[k][o] = float(kv);
-                if ((ii | jj) & 1) break;
-                ii >>= 1;
-                jj >>= 1;
-                nl >>= 1;
             }
         }
         __syncthreads();
