@@ -259,8 +259,12 @@ def test_fp64_nu1_smoothing():
 
 
 # ------------------------------------------------------------ FP32 + FP64 IR
-@pytest.mark.parametrize("level,S", [(0, 24), (2, 8), (3, 4)])
+@pytest.mark.parametrize("level,S", [(0, 24), (1, 16), (2, 8), (3, 4)])
 def test_ir_matches_oracle_to_1e8(level, S):
+    """FP32 cycles + FP64 refinement driven to 1e-12 against the oracle: level 0
+    (32^2 top grid, cycled in LDS), level 1 (64^2 top grid whose first refinement
+    pass forms its start from the 32^2 stage solved in LDS, and writes its
+    correction faces), levels 2 and 3."""
     cfg = CFG2
     n = cfg["n0"] << level
     xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level)
