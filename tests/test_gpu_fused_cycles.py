@@ -95,17 +95,32 @@ def test_fused_matches_separate_and_oracle(nu):
 
 
 def test_fused_case1_matches_oracle():
+    """Case I (Dirichlet on every side). The fused path's top-stage first refinement
+    also forms the start (with the Dirichlet ghost rows) and the correction faces
+    (with the north boundary faces): a wrong boundary value there would still
+    converge under the refinement, but in more cycles, so the fused and separate
+    paths must take the same cycle counts (up to a rounding tie) as well as agree
+    on Q."""
     cfg = CFG2
     level, S = 2, 6
     n = cfg["n0"] << level
     xi = inputs.mc_normals(S, cfg["n_modes"], config=2, level=level, purpose=1)
     log(f"fused FP32 cycles, Case I, n {n} S {S}")
-    with fmgmc.Context(**cfg, solver="fp32_ir", rel_tol=1e-12, max_cycles=80, inner_first=4, case=1) as ctx:
-        rc, qf, qc, cyc, fl, prof = run(ctx, level, xi)
-    assert rc == fmgmc.OK and np.all(fl == 0) and prof["fused"][1] == 3
+    out = {}
+    for fuse in (True, False):
+        with fmgmc.Context(**cfg, solver="fp32_ir", rel_tol=1e-12, max_cycles=80, inner_first=4, case=1,
+                           fuse_cycles=fuse) as ctx:
+            out[fuse] = run(ctx, level, xi)
+    rc, qf, qc, cyc, fl, prof = out[True]
+    rc0, qf0, qc0, cyc0, fl0, prof0 = out[False]
+    assert rc == fmgmc.OK and np.all(fl == 0) and prof["fused"][1] == 3 and prof["irpre"][1] > 0
+    assert rc0 == fmgmc.OK and np.all(fl0 == 0)
+    assert np.sum(np.any(cyc != cyc0, axis=1)) <= 1 and np.all(np.abs(cyc - cyc0) <= 1)
+    d = max(np.max(np.abs(qf - qf0) / np.abs(qf0)), np.max(np.abs(qc - qc0) / np.abs(qc0)))
     oqf, oqc, _, _ = oracle(cfg, n, level, xi, tol=1e-12, max_cycles=80, case=1)
     e = max(np.max(np.abs(qf - oqf) / np.abs(oqf)), np.max(np.abs(qc - oqc) / np.abs(oqc)))
-    log(f"  vs oracle {e:.2e}")
+    log(f"  vs oracle {e:.2e}; fused vs separate {d:.2e}; cycles {cyc.mean(axis=0)} / {cyc0.mean(axis=0)}")
+    assert d <= 1e-9
     assert e <= 1e-8
 
 
