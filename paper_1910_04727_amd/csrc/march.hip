@@ -40,6 +40,20 @@ __device__ __forceinline__ T harm(T a, T b) {
     return T(2) * a * b * rcp_(a + b);
 }
 
+// c ? a : b with both operands evaluated on every lane: the compiler otherwise
+// guards the costlier one (a neighbour's load, a harmonic mean) by an
+// exec-mask branch, for the single lane at a side of the grid
+template <typename T>
+__device__ __forceinline__ T lane_sel(bool c, T a, T b) {
+    if constexpr (sizeof(T) == 4) {
+        const uint32_t m = 0u - uint32_t(c);
+        return __builtin_bit_cast(T, (__builtin_bit_cast(uint32_t, a) & m) | (__builtin_bit_cast(uint32_t, b) & ~m));
+    } else {
+        const uint64_t m = 0ull - uint64_t(c);
+        return __builtin_bit_cast(T, (__builtin_bit_cast(uint64_t, a) & m) | (__builtin_bit_cast(uint64_t, b) & ~m));
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ V2<T> ld2(const T *p) {
     if constexpr (sizeof(T) == 8) {
@@ -237,10 +251,10 @@ void k_march(MarchArgs<T> A) {
         const int J0 = R >> 1, J1 = J0 + ((R & 1) ? 1 : -1);
         const double *c0 = cs64 + (J0 & 3) * nc, *c1 = cs64 + (J1 & 3) * nc;
         const double a0 = c0[l], a1 = c1[l];
-        const double w0 = first ? 2.0 * A.g.w - a0 : c0[max(l - 1, 0)];
-        const double w1 = first ? 2.0 * A.g.w - a1 : c1[max(l - 1, 0)];
-        const double e0 = last ? 2.0 * A.g.e - a0 : c0[min(l + 1, nc - 1)];
-        const double e1 = last ? 2.0 * A.g.e - a1 : c1[min(l + 1, nc - 1)];
+        const double w0 = lane_sel(first, 2.0 * A.g.w - a0, c0[max(l - 1, 0)]);
+        const double w1 = lane_sel(first, 2.0 * A.g.w - a1, c1[max(l - 1, 0)]);
+        const double e0 = lane_sel(last, 2.0 * A.g.e - a0, c0[min(l + 1, nc - 1)]);
+        const double e1 = lane_sel(last, 2.0 * A.g.e - a1, c1[min(l + 1, nc - 1)]);
         const double p0 = (9.0 * a0 + 3.0 * w0 + 3.0 * a1 + w1) / 16.0;
         const double p1 = (9.0 * a0 + 3.0 * e0 + 3.0 * a1 + e1) / 16.0;
         st2_nt(A.p + base + size_t(R) * n + 2 * l, p0, p1);
