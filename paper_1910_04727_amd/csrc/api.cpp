@@ -345,7 +345,13 @@ Bufs<float> bufs32(Work &w) { return {w.K32, w.x32, w.b32, w.pf32}; }
 // VC_SKIP_PRE, the previous cycle's last pass already did this cycle's
 // pre-smoothing and restriction; VC_FUSE_POST, the post-smoothing pass also
 // does the next cycle's pre-smoothing and restriction.
-enum { VC_SKIP_PRE = 1, VC_FUSE_POST = 2 };
+template <typename T>
+int pyramid(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int q, int top, bool from_k, hipStream_t st);
+
+enum { VC_SKIP_PRE = 1, VC_FUSE_POST = 2, VC_TOP_FACES = 4 };
+// VC_TOP_FACES (the FP64 form's top stage, level >= 1): its first pre-smoothing
+// pass also writes the faces on n/2 of the stage's correction pyramid (skipped by
+// prepare), which is then finished before the coarse-grid correction.
 
 // One cycle with top grid k: top operator from K (stage operator), the levels
 // below from correction pyramid q; V(nu1,nu2) on grids above w_max_n, two
@@ -391,7 +397,7 @@ int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool
         a.x = B.x[j];
         a.b = B.b[j];
         a.K = B.K[j];
-        a.f = B.pf[q].f[j];
+        a.f = (mout & OUT_FACES) ? B.pf[1].f[j - 1] : B.pf[q].f[j];
         a.xc = B.x[j - 1];
         a.bc = B.b[j - 1];
         a.rr = W.rr;
@@ -415,8 +421,12 @@ int vcycle(fmgmc_ctx *c, Work &W, Bufs<T> B, int S, int k, int q, int init, bool
                          (rhs_array ? w : 0.0) + w /*x out*/ + 0.25 * w /*restricted residual*/;
     const double b_post = w + 0.25 * w + w + (rhs_array ? w : 0.0) + w;
     if (!(flow & VC_SKIP_PRE)) {
-        if (top) TRY(timed(c, W, FMGMC_PROF_PRE, act * cells * b_pre, st, [&] { return march(k, true, init, rhs_array, OUT_RESTRICT, nh1); }));
-        else TRY(march(k, true, init, rhs_array, OUT_RESTRICT, nh1));
+        const int out_pre = OUT_RESTRICT | ((flow & VC_TOP_FACES) ? OUT_FACES : 0);
+        // (the faces: west and south on n/2, a quarter of the cells each)
+        const double b_faces = (flow & VC_TOP_FACES) ? 0.5 * w : 0.0;
+        if (top) TRY(timed(c, W, FMGMC_PROF_PRE, act * cells * (b_pre + b_faces), st, [&] { return march(k, true, init, rhs_array, out_pre, nh1); }));
+        else TRY(march(k, true, init, rhs_array, out_pre, nh1));
+        if (flow & VC_TOP_FACES) TRY(pyramid<T>(c, W, B, S, 1, k, false, st));
     }
     for (int g = 0; g < gamma(k - 1); ++g) TRY(corr(k - 1, g == 0 ? INIT_ZERO : INIT_LOAD));
     if (flow & VC_FUSE_POST) {
@@ -595,7 +605,10 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
                    hipStream_t st) {
     const int t = ilog2((c->hier.n0 << level) / W.nsz[0]);
     Bufs<double> B = bufs64(W);
-    TRY(prepare<double>(c, W, B, S, level, t, st));
+    // the top stage's first pass writes the faces on n/2 of its pyramid (pyramid 1
+    // serves only the top stage when level >= 1)
+    const bool top_faces = level >= 1 && t > c->small_top;
+    TRY(prepare<double>(c, W, B, S, level, t, st, top_faces));
     const double tol = c->opts.rel_tol;
     // one FMG pass up to stage ktop; with_coarse: stage ktop - 1 is a QoI stage too
     auto pass = [&](int ktop, bool with_coarse, double *qtop, int slot_top) -> int {
@@ -618,7 +631,8 @@ int run_batch_fp64(fmgmc_ctx *c, Work &W, const Tune &tn, int level, int S, doub
                 TRY(read_active(W, st, &na));
                 continue;
             }
-            TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st));
+            TRY(vcycle<double>(c, W, B, S, k, q, INIT_INTERP, false, OUT_RR | OUT_Q, st,
+                               (top_faces && k == t) ? VC_TOP_FACES : 0));
             TRY(launch_checks(c, W, S, slot, qout, 1, tol, st));
             TRY(iterate_stage(c, W, tn, level, k, S, 1, 1, -1, st, [&]() -> int {
                 TRY(vcycle<double>(c, W, B, S, k, q, INIT_LOAD, false, OUT_RR | OUT_Q, st));

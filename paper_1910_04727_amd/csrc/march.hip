@@ -147,7 +147,8 @@ void k_march(MarchArgs<T> A) {
                   "the refinement start is an FP32 pre-smoothing pass of the stage operator");
     // OUT_FACES: coarse faces written as the coefficients of each odd row are formed
     constexpr bool FO = (OUT & OUT_FACES) != 0;
-    static_assert(!FO || (IR && !(OUT & OUT_PUPD)), "faces are written by the stage's first refinement");
+    static_assert(!FO || (IR && !(OUT & OUT_PUPD)) || (CK && INIT == INIT_INTERP && !RHSA),
+                  "faces are written by the top stage's first pass");
     // OUT_PINTERP: row F + 1 of p formed at step F from a 4-row LDS ring of coarse
     // rows (slot = row & 3; the ghost rows -1 and n/2 in slots 3 and (n/2) & 3):
     // coarse row (F + 3) / 2 enters at odd steps F (rows 0 and 1 before the
@@ -451,6 +452,10 @@ static int dispatch_march(const MarchArgs<T> &a, int S, bool ck, int init, bool 
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_FACES)
             FMGMC_MARCH_CASE(true, INIT_IR, true, OUT_RESTRICT | OUT_FACES | OUT_PINTERP)
         }
+    }
+    if constexpr (sizeof(T) == 8) {
+        // the FP64 form's top stage: its first pass also writes the faces on n/2
+        FMGMC_MARCH_CASE(true, INIT_INTERP, false, OUT_RESTRICT | OUT_FACES)
     }
     // correction operators (levels below the top)
     FMGMC_MARCH_CASE(false, INIT_ZERO, true, OUT_RESTRICT)
