@@ -110,8 +110,8 @@ def test_512_batch_sampled_against_oracle(solver, tol, bound):
     with fmgmc.Context(**cfg, solver=solver, rel_tol=tol, max_batch=S, max_cycles=80, case=1) as ctx:
         rc, qf, qc, cyc, fl = run_level(ctx, level, xi)
     assert rc == fmgmc.OK and np.all(fl == 0)
-    pick = [0, 63, 127]
-    oqf, oqc, ocyc, _ = oracle(cfg, 512, level, xi[pick], tol=tol, max_cycles=80, nthreads=3)
+    pick = list(range(0, S, 8)) + [S - 1]
+    oqf, oqc, ocyc, _ = oracle(cfg, 512, level, xi[pick], tol=tol, max_cycles=80, nthreads=O.max_threads())
     log(f"  cycles gpu {cyc[pick].tolist()} oracle {ocyc.tolist()}")
     if solver == "fp64":
         assert_same_solution(qf[pick], oqf, cyc[pick][:, 1:], ocyc[:, 1:], bound, "  qf")

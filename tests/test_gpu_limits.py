@@ -54,10 +54,10 @@ def test_benchmark_launch_configuration_sampled_against_oracle():
                        inner_first=4, inner_cycles=1) as ctx:
         rc, qf, qc, cyc, fl = run(ctx, level, xi)
     assert rc == fmgmc.OK and np.all(fl == 0)
-    pick = [0, 1365, 2730, 4095]
+    pick = list(range(0, S, 64)) + [S - 1]  # 65 samples across the batch, both ends included
     tab = O.kl_table(cfg["sigma2"], cfg["corr_len"], cfg["n_modes"])
     oqf, oqc, _, _ = O.solve_level(cfg["sigma2"], cfg["corr_len"], tab, 512, level, xi[pick], tol=1e-12,
-                                   max_cycles=80, nthreads=4)
+                                   max_cycles=80, nthreads=O.max_threads())
     ef = np.abs(qf[pick] - oqf) / np.abs(oqf)
     ec = np.abs(qc[pick] - oqc) / np.abs(oqc)
     log(f"  max rel err qf {ef.max():.2e} qc {ec.max():.2e}; cycles {cyc.mean(0)}")
