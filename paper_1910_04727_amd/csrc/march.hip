@@ -126,13 +126,16 @@ void k_march(MarchArgs<T> A) {
     // step F + D reads): U rows; three in the FP32 stage-grid passes of eight
     // half-sweeps, whose registers then fit three waves per SIMD (see RC
     // below; 7% faster so); one in the correction passes (coefficients from
-    // faces, grids below the stage grid), whose row steps are long enough to
-    // cover a load. The registers that frees (FP32 with RI below: 145-152 ->
-    // 99-109 VGPRs; FP64: 244-256 with a spill -> 186-194 without) take the FP32
-    // passes to four waves per SIMD, so that all 4096 one-wave workgroups of a
-    // 128^2 or 64^2 pass are resident at once (FP32+IR +1.3-2.7%, FP64 form
-    // +1.8%, same-box A/B).
-    constexpr int D = !CK ? 1 : (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3 : U;
+    // faces, grids below the stage grid) and in every FP64 pass, whose row
+    // steps are long enough to cover a load. The registers that frees (FP32
+    // with RI below: 145-152 -> 99-109 VGPRs; FP64 correction passes: 244-256
+    // with a spill -> 186-194 without) take the FP32 passes to four waves per
+    // SIMD, so that all 4096 one-wave workgroups of a 128^2 or 64^2 pass are
+    // resident at once (FP32+IR +1.3-2.7%, FP64 form +1.8%, same-box A/B); in
+    // the FP64 stage-operator passes (190-220 -> 152-196 VGPRs) the 512^2
+    // post-smoothing pass then takes 9% less time (FP64 form +2.5%, bitwise
+    // unchanged).
+    constexpr int D = !CK ? 1 : (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3 : (sizeof(T) == 8) ? 1 : U;
     static_assert(U % D == 0, "the load queue depth must divide the unroll");
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
@@ -296,10 +299,10 @@ void k_march(MarchArgs<T> A) {
     // acted on last; hv[0], the row that entered last; hres, the row below the
     // residual's row), so that the sweeps read only the west / east neighbours
     // from LDS. In FP64 that halves the LDS traffic that bounds these passes (two
-    // waves per SIMD either way: 206 VGPRs and 58 KB of LDS at 512^2 for the
-    // stage operator; 218-238 VGPRs for the correction passes, which fit it
-    // without a spill since their load queue holds one row: +0.7%, bitwise
-    // unchanged). The other passes read them from the LDS ring: their register
+    // waves per SIMD either way: 58 KB of LDS per 512^2 stage-operator workgroup
+    // leave room for two per CU; 218-238 VGPRs for the correction passes, which
+    // fit it without a spill since their load queue holds one row: +0.7%,
+    // bitwise unchanged). The other passes read them from the LDS ring: their register
     // rings leave no room (the FP32 eight-half-sweep pass drops from 252 VGPRs,
     // two waves per SIMD, to 162, three; the refinement start, whose FP64 state
     // takes the room, keeps three waves per SIMD so, at 156-163 VGPRs).
