@@ -126,16 +126,16 @@ void k_march(MarchArgs<T> A) {
     // step F + D reads): U rows; three in the FP32 stage-grid passes of eight
     // half-sweeps, whose registers then fit three waves per SIMD (see RC
     // below; 7% faster so); one in the correction passes (coefficients from
-    // faces, grids below the stage grid) and in every FP64 pass, whose row
-    // steps are long enough to cover a load. The registers that frees (FP32
-    // with RI below: 145-152 -> 99-109 VGPRs; FP64 correction passes: 244-256
-    // with a spill -> 186-194 without) take the FP32 passes to four waves per
-    // SIMD, so that all 4096 one-wave workgroups of a 128^2 or 64^2 pass are
-    // resident at once (FP32+IR +1.3-2.7%, FP64 form +1.8%, same-box A/B); in
-    // the FP64 stage-operator passes (190-220 -> 152-196 VGPRs) the 512^2
-    // post-smoothing pass then takes 9% less time (FP64 form +2.5%, bitwise
-    // unchanged).
-    constexpr int D = !CK ? 1 : (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3 : (sizeof(T) == 8) ? 1 : U;
+    // faces, grids below the stage grid) and in the FP64 post-smoothing passes
+    // of the stage operator, whose row steps are long enough to cover a load.
+    // The registers that frees (FP32 with RI below: 145-152 -> 99-109 VGPRs;
+    // FP64 correction passes: 244-256 with a spill -> 186-194 without) take the
+    // FP32 passes to four waves per SIMD, so that all 4096 one-wave workgroups
+    // of a 128^2 or 64^2 pass are resident at once (FP32+IR +1.3-2.7%, FP64
+    // form +1.8%, same-box A/B), and let the FP64 post-smoothing pass run
+    // straight-line steps (see the row loops).
+    constexpr int D = !CK ? 1 : (sizeof(T) == 4 && U % 3 == 0 && NH >= 6) ? 3
+                    : (sizeof(T) == 8 && INIT == INIT_PROLONG) ? 1 : U;
     static_assert(U % D == 0, "the load queue depth must divide the unroll");
     constexpr bool RES = (OUT & (OUT_RESTRICT | OUT_RR)) != 0;
     constexpr bool CO = (INIT == INIT_PROLONG || INIT == INIT_INTERP);
@@ -322,8 +322,11 @@ void k_march(MarchArgs<T> A) {
     // conditional and no wait for outstanding loads is forced at a merge; the
     // step is a lambda there (that keeps these kernels within 128 registers).
     // FP64: the step inline in the loops (behind a lambda the compiler kept one
-    // of its queues in scratch memory); straight-line steps only in the
-    // pre-smoothing passes of the stage operator, checked steps elsewhere.
+    // of its queues in scratch memory); straight-line steps in the passes of the
+    // stage operator, checked steps in the correction passes. The post-smoothing
+    // pass spills 100 B per lane so (256 VGPRs, two waves per SIMD as before, which
+    // its LDS sets at 512^2) and still takes 10% less time than with checked steps
+    // (FP64 form +4%, bitwise unchanged, same-box A/B).
     if constexpr (sizeof(T) == 4) {
         auto step = [&](const int F, const int u, auto chk) __attribute__((always_inline)) {
             constexpr bool C = decltype(chk)::value;
@@ -347,9 +350,8 @@ void k_march(MarchArgs<T> A) {
             for (int u = 0; u < U; ++u)
                 if (F0 + u <= LAST) step(F0 + u, u, std::true_type{});
         }
-    } else if constexpr (CK && INIT != INIT_PROLONG) {
-        // FP64 stage-operator passes that start from x (pre-smoothing): their rings
-        // leave room for the straight-line steps (the other FP64 passes would spill)
+    } else if constexpr (CK) {
+        // FP64 stage-operator passes
         const int lo = ((NH + 1 + U - 1) / U) * U;
         const int hi = max(lo, ((n - U) / U) * U);
         int F0 = 0;
