@@ -322,11 +322,12 @@ void k_march(MarchArgs<T> A) {
     // conditional and no wait for outstanding loads is forced at a merge; the
     // step is a lambda there (that keeps these kernels within 128 registers).
     // FP64: the step inline in the loops (behind a lambda the compiler kept one
-    // of its queues in scratch memory); straight-line steps in the passes of the
-    // stage operator, checked steps in the correction passes. The post-smoothing
-    // pass spills 100 B per lane so (256 VGPRs, two waves per SIMD as before, which
-    // its LDS sets at 512^2) and still takes 10% less time than with checked steps
-    // (FP64 form +4%, bitwise unchanged, same-box A/B).
+    // of its queues in scratch memory), with the same checked and straight-line
+    // steps. The stage operator's post-smoothing pass spills 100 B per lane so
+    // (256 VGPRs, two waves per SIMD as before, which its LDS sets at 512^2) and
+    // still takes 10% less time than with checked steps throughout (FP64 form
+    // +4%); the correction passes (198-206 VGPRs, no spill) gave another +2.4%
+    // (bitwise unchanged, same-box A/B).
     if constexpr (sizeof(T) == 4) {
         auto step = [&](const int F, const int u, auto chk) __attribute__((always_inline)) {
             constexpr bool C = decltype(chk)::value;
@@ -350,8 +351,7 @@ void k_march(MarchArgs<T> A) {
             for (int u = 0; u < U; ++u)
                 if (F0 + u <= LAST) step(F0 + u, u, std::true_type{});
         }
-    } else if constexpr (CK) {
-        // FP64 stage-operator passes
+    } else {
         const int lo = ((NH + 1 + U - 1) / U) * U;
         const int hi = max(lo, ((n - U) / U) * U);
         int F0 = 0;
@@ -373,16 +373,6 @@ void k_march(MarchArgs<T> A) {
             }
         }
         for (; F0 <= LAST; F0 += U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int F = F0 + u;
-                if (F > LAST) break;
-                constexpr bool C = true;
-#include "march_step.inc"
-            }
-        }
-    } else {
-        for (int F0 = 0; F0 <= LAST; F0 += U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int F = F0 + u;
