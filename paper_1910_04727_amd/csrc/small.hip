@@ -16,6 +16,16 @@ namespace {
 
 constexpr int kMaxLev = 4;   // 4, 8, 16, 32
 constexpr int kThreads = 256;
+// FP64: the top grid's right-hand side is not kept in LDS (a lane reads only
+// its own cells' values): the kSw cells of each colour that a lane updates in
+// a half-sweep hold theirs in registers (n <= 32: n^2 / 2 <= kSw kThreads);
+// the restriction and the residual norm, once per call, read or form it again.
+// A 32^2 sample then takes 36 KB of LDS instead of 44 KB, four per CU instead
+// of three (k_small<double> 210 -> 186 us per 4096-sample call, bitwise
+// unchanged). In FP32 the same registers took the kernel from 62 to 77 VGPRs,
+// six waves per SIMD instead of eight, and it ran slower (118 -> 135 us; capped
+// at 64 VGPRs it spilled, 146 us), so FP32 keeps it in LDS (seven samples per CU).
+constexpr int kSw = 2;
 
 template <typename T>
 __device__ __forceinline__ T harm_s(T a, T b) {
@@ -84,16 +94,16 @@ __device__ __forceinline__ T prolong_at(const T *c, int nc, int lgc, int i, int 
     return (T(9) * a + T(3) * bx + T(3) * by + bxy) / T(16);
 }
 
-// sum over interior neighbours of T_nb x_nb, plus b (a side without an
-// interior neighbour adds 0 * x of the cell itself, so every lane runs the
-// same instructions and the sum keeps its order)
+// sum over interior neighbours of T_nb x_nb, plus the right-hand side bv of
+// the cell (a side without an interior neighbour adds 0 * x of the cell
+// itself, so every lane runs the same instructions and the sum keeps its order)
 template <typename T>
-__device__ __forceinline__ T nbsum(const Lv<T> &L, int i, int j) {
+__device__ __forceinline__ T nbsum(const Lv<T> &L, int i, int j, T bv) {
     const int n = L.n, P = j * n + i;
     const bool w = i > 0, e = i < n - 1, so = j > 0, no = j < n - 1;
     const T tw = w ? L.fx[P] : T(0), te = e ? L.fx[P + 1] : T(0);
     const T ts = so ? L.fy[P] : T(0), tn = no ? L.fy[P + n] : T(0);
-    T acc = L.b[P];
+    T acc = bv;
     acc += tw * L.x[w ? P - 1 : P];
     acc += te * L.x[e ? P + 1 : P];
     acc += ts * L.x[so ? P - n : P];
@@ -109,21 +119,33 @@ __device__ __forceinline__ T diag(const Lv<T> &L, int i, int j) {
     return ((L.fx[P] + te) + L.fy[P]) + tn;
 }
 
-template <typename T>
-__device__ void half_sweep(const Lv<T> &L, int colour, int tid) {
+// right-hand side from bt[m] (breg: the top grid's, in registers) or L.b
+template <typename T, int COLOUR>
+__device__ __forceinline__ void half_sweep(const Lv<T> &L, int tid, const T (&bt)[kSw], bool breg) {
     const int n = L.n, h = n >> 1;
-    for (int c = tid; c < n * h; c += kThreads) {
-        const int j = c >> (L.lg - 1), i = 2 * (c & (h - 1)) + ((j + colour) & 1);
-        L.x[j * n + i] = nbsum(L, i, j) * rcp_(diag(L, i, j));
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int m = 0; m < kSw; ++m) {
+            const int c = tid + m * kThreads;
+            if (c < n * h) {
+                const int j = c >> (L.lg - 1), i = 2 * (c & (h - 1)) + ((j + COLOUR) & 1);
+                L.x[j * n + i] = nbsum(L, i, j, breg ? bt[m] : L.b[j * n + i]) * rcp_(diag(L, i, j));
+            }
+        }
+    } else {
+        for (int c = tid; c < n * h; c += kThreads) {
+            const int j = c >> (L.lg - 1), i = 2 * (c & (h - 1)) + ((j + COLOUR) & 1);
+            L.x[j * n + i] = nbsum(L, i, j, L.b[j * n + i]) * rcp_(diag(L, i, j));
+        }
     }
     __syncthreads();
 }
 
 template <typename T>
-__device__ void smooth(const Lv<T> &L, int nu, int tid) {
+__device__ void smooth(const Lv<T> &L, int nu, int tid, const T (&bt)[2][kSw], bool breg) {
     for (int k = 0; k < nu; ++k) {
-        half_sweep(L, 0, tid);
-        half_sweep(L, 1, tid);
+        half_sweep<T, 0>(L, tid, bt[0], breg);
+        half_sweep<T, 1>(L, tid, bt[1], breg);
     }
 }
 
@@ -151,6 +173,9 @@ __device__ void coarse_solve(const double *Ainv, const T *b, T *x, int tid) {
 }
 
 template <typename T>
+__host__ __device__ constexpr bool small_rhs_in_registers(int top) { return sizeof(T) == 8 && top > 0; }
+
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bool rhs_array, int out) {
     const int s = blockIdx.x;
     if (A.active && A.active[s] == 0) return;
@@ -158,8 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
     extern __shared__ unsigned char smem_raw[];
     T *const base = reinterpret_cast<T *>(smem_raw);
     const int top = A.top;
-    // level k arrays (x, b, fx, fy of n*n, then fxe and fyn of n), packed from level 0 up;
-    // 1/diagonal is recomputed where needed, which keeps more samples resident per CU
+    // FP64: the top grid's right-hand side in registers (above the coarsest grid,
+    // whose direct solve reads all of it in every lane)
+    const bool breg = small_rhs_in_registers<T>(top);
+    // level k arrays (x, b, fx, fy of n*n, then fxe and fyn of n; no b on the top
+    // grid with breg), packed from level 0 up; 1/diagonal is recomputed where
+    // needed: both keep more samples resident per CU
     auto lv = [&](int k) -> Lv<T> {
         T *p = base;
         for (int j = 0; j < k; ++j) p += 4 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
@@ -168,7 +197,12 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         L.n = n;
         L.lg = __builtin_ctz(n);
         L.x = p; p += n * n;
-        L.b = p; p += n * n;
+        if (k == top && breg) {
+            L.b = nullptr;
+        } else {
+            L.b = p;
+            p += n * n;
+        }
         L.fx = p; p += n * n;
         L.fy = p; p += n * n;
         L.fxe = p; p += n;
@@ -176,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         return L;
     };
     T *p = base;
-    for (int j = 0; j <= top; ++j) p += 4 * A.ns[j] * A.ns[j] + 2 * A.ns[j];
+    for (int j = 0; j <= top; ++j) p += ((j == top && breg) ? 3 : 4) * A.ns[j] * A.ns[j] + 2 * A.ns[j];
     T *red = p;
     const int N0 = A.ns[0] * A.ns[0];
     const double *Ls = A.chol + size_t(s) * N0 * N0;
@@ -214,23 +248,38 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
         }
     }
     __syncthreads();
-    // right-hand side and initial guess on the top level
+    // right-hand side of the top grid at cell (i, j): the array, or the boundary
+    // data through the boundary faces
+    const Lv<T> Tp = lv(top);
+    auto top_rhs = [&](int i, int j) -> T {
+        const int n = Tp.n, c = j * n + i;
+        if (rhs_array) return A.b[size_t(s) * n * n + c];
+        T b0 = T(0);
+        if (i == 0) b0 += Tp.fx[c] * gsol.w;
+        if (i == n - 1) b0 += Tp.fxe[j] * gsol.e;
+        if (dns && j == 0) b0 += Tp.fy[c] * gsol.s;
+        if (dns && j == n - 1) b0 += Tp.fyn[i] * gsol.n;
+        return b0;
+    };
+    // right-hand side (in LDS, or the half-sweeps' cells in registers) and
+    // initial guess on the top level
+    T bsw[2][kSw];
     {
-        const Lv<T> Tp = lv(top);
-        const int n = Tp.n, nn = n * n;
+        const int n = Tp.n, nn = n * n, h = n >> 1;
+        if (breg) {
+#pragma unroll
+            for (int col = 0; col < 2; ++col)
+#pragma unroll
+                for (int m = 0; m < kSw; ++m) {
+                    const int c = tid + m * kThreads;
+                    const int j = c >> (Tp.lg - 1), i = 2 * (c & (h - 1)) + ((j + col) & 1);
+                    bsw[col][m] = c < n * h ? top_rhs(i, j) : T(0);
+                }
+        }
 #pragma unroll 4
         for (int c = tid; c < nn; c += kThreads) {
             const int i = c & (n - 1), j = c >> Tp.lg;
-            if (rhs_array) {
-                Tp.b[c] = A.b[size_t(s) * nn + c];
-            } else {
-                T b0 = T(0);
-                if (i == 0) b0 += Tp.fx[c] * gsol.w;
-                if (i == n - 1) b0 += Tp.fxe[j] * gsol.e;
-                if (dns && j == 0) b0 += Tp.fy[c] * gsol.s;
-                if (dns && j == n - 1) b0 += Tp.fyn[i] * gsol.n;
-                Tp.b[c] = b0;
-            }
+            if (!breg) Tp.b[c] = top_rhs(i, j);
             T xv = T(0);
             if (init == INIT_LOAD) xv = A.x[size_t(s) * nn + c];
             else if (init == INIT_INTERP) xv = interp_at(A.xc + size_t(s) * (nn / 4), n / 2, i, j, gsol);
@@ -257,15 +306,17 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
                 continue;
             }
             const Lv<T> Lk = lv(k), Lc = lv(k - 1);
-            smooth(Lk, A.nu1, tid);
+            const bool kb = breg && k == top;
+            smooth(Lk, A.nu1, tid, bsw, kb);
             const int n = Lk.n, nc = n / 2;
-            for (int c = tid; c < nc * nc; c += kThreads) {
+            for (int c = tid; c < nc * nc; c += kThreads) {  // one coarse cell per lane
                 const int I = c & (nc - 1), J = c >> (Lk.lg - 1);
                 T acc = T(0);
                 for (int dj = 0; dj < 2; ++dj)
                     for (int di = 0; di < 2; ++di) {
                         const int i = 2 * I + di, j = 2 * J + dj;
-                        acc += nbsum(Lk, i, j) - diag(Lk, i, j) * Lk.x[j * n + i];
+                        const T bv = kb ? top_rhs(i, j) : Lk.b[j * n + i];
+                        acc += nbsum(Lk, i, j, bv) - diag(Lk, i, j) * Lk.x[j * n + i];
                     }
                 Lc.b[c] = acc;
                 Lc.x[c] = T(0);
@@ -287,21 +338,20 @@ __global__ __launch_bounds__(kThreads) void k_small(SmallArgs<T> A, int init, bo
             for (int c = tid; c < n * n; c += kThreads)
                 Lk.x[c] += prolong_at(Lc.x, nc, Lc.lg, c & (n - 1), c >> Lk.lg, dns);
             __syncthreads();
-            smooth(Lk, A.nu2, tid);
+            smooth(Lk, A.nu2, tid, bsw, breg && k == top);
             if (k == top) break;
             k = k + 1;
         }
     }
 
     // outputs
-    const Lv<T> Tp = lv(top);
     const int n = Tp.n, nn = n * n;
     for (int c = threadIdx.x; c < nn; c += kThreads) A.x[size_t(s) * nn + c] = Tp.x[c];
     if (out & OUT_RR) {
         T rr = T(0);
         for (int c = threadIdx.x; c < nn; c += kThreads) {
             const int i = c & (n - 1), j = c >> Tp.lg;
-            const T r = nbsum(Tp, i, j) - diag(Tp, i, j) * Tp.x[c];
+            const T r = nbsum(Tp, i, j, breg ? top_rhs(i, j) : Tp.b[c]) - diag(Tp, i, j) * Tp.x[c];
             rr += r * r;
         }
         for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
@@ -336,7 +386,9 @@ int launch_small(const SmallArgs<T> &a, int S, int init, bool rhs_array, int out
     }
     if (S <= 0) return FMGMC_OK;
     size_t words = 0;
-    for (int k = 0; k <= a.top; ++k) words += 4 * size_t(a.ns[k]) * a.ns[k] + 2 * size_t(a.ns[k]);
+    for (int k = 0; k <= a.top; ++k)
+        words += ((k == a.top && small_rhs_in_registers<T>(a.top)) ? 3 : 4) * size_t(a.ns[k]) * a.ns[k] +
+                 2 * size_t(a.ns[k]);
     const size_t bytes = (words + 8) * sizeof(T);  // the levels, then 8 reduction slots
     hipLaunchKernelGGL(k_small<T>, dim3(S), dim3(kThreads), bytes, st, a, init, rhs_array, out);
     return hipGetLastError() == hipSuccess ? FMGMC_OK : FMGMC_EHIP;
